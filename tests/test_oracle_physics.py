@@ -1,0 +1,183 @@
+"""Pins of the oracle against results the paper and the textbook limits fix.
+
+* Force geometry: Eq. (2) with Table I on a single-site perturbation, and the
+  paper's sign convention (G > 0 repels, G < 0 attracts, Sec. II).
+* Long-wavelength force: the lattice sums reduce to c_s^2 G_s1 grad psi plus a
+  third-derivative term with G_s2 (Sec. III, Eqs. (14)-(17)), isotropically.
+* Single-phase limit: shear waves decay with nu = c_s^2 (tau - 1/2) (Sec. VI:
+  tau = 1 <-> nu = 1/6), with the mixture relaxation time of the Sec. III
+  footnote when tau_A != tau_B.
+* Couette flow between moving walls: linear profile and wall stress rho nu du/dy.
+* Pure-repulsion bulk densities of a flat interface: Eq. (30) with the
+  tau-renormalised rho_g of Eq. (29).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from conftest import read_golden
+from oracle import theory
+from paper_0906_3611_amd import inputs
+
+CS2 = 1.0 / 3.0
+
+
+def _table1():
+    """Weights by class |c|^2, from the Table I fixture."""
+    p, w = {}, {}
+    for row in read_golden("table1_weights.txt"):
+        kind, c, _, num, den = row.split()
+        (p if kind == "p" else w)[int(c)] = int(num) / int(den)
+    return p, w
+
+
+def _offsets():
+    return [(x, y) for y in range(-2, 3) for x in range(-2, 3) if (x, y) != (0, 0)]
+
+
+@pytest.mark.parametrize("Ga,Gr,Gab", [(-2.0, 1.5, 0.7), (1.0, 0.0, 0.0), (0.0, -1.0, -0.5)])
+def test_single_site_force_geometry(Ga, Gr, Gab):
+    """A lone density excess at r0 acts on every site r = r0 - c along c with
+    weight G^a w + G^r p of the class of c (species A), and on species B
+    through the cross term with weight G_AB w / rho0^2."""
+    P, W = _table1()
+    n, rho0, base, d = 9, 0.9, 0.5, 0.03
+    p = oracle.Params(nx=n, ny=n, tau=(1.0, 1.0), rho0=rho0, Ga=(Ga, 0.3), Gr=(Gr, -0.2), Gab=Gab)
+    rho = np.full((2, n, n), base)
+    x0 = y0 = 4
+    rho[0, y0, x0] += d
+    F = oracle.force(p, rho)
+    psib = rho0 * (1 - math.exp(-base / rho0))
+    dpsi = rho0 * (1 - math.exp(-(base + d) / rho0)) - psib
+    seen = set()
+    for cxk, cyk in _offsets():
+        c2 = cxk * cxk + cyk * cyk
+        x, y = x0 - cxk, y0 - cyk
+        seen.add((x, y))
+        kA = Ga * W.get(c2, 0.0) + Gr * P[c2]
+        expA = -psib * kA * dpsi * np.array([cxk, cyk])
+        expB = -(Gab / rho0 ** 2) * base * W.get(c2, 0.0) * d * np.array([cxk, cyk])
+        assert np.allclose(F[0, :, y, x], expA, rtol=1e-12, atol=1e-15), (cxk, cyk)
+        assert np.allclose(F[1, :, y, x], expB, rtol=1e-12, atol=1e-15), (cxk, cyk)
+    for y in range(n):
+        for x in range(n):
+            if (x, y) not in seen:
+                assert np.abs(F[:, :, y, x]).max() < 1e-15
+    # sign convention of Sec. II: G > 0 pushes the neighbours away from the excess
+    if Ga > 0 and Gr == 0:
+        assert F[0, 0, y0, x0 - 1] < 0 and F[0, 0, y0, x0 + 1] > 0
+
+
+def _symbol(Ga, Gr, k):
+    """Two-term expansion of sum_i (G^a w_i + G^r p_i) c_i sin(k . c_i) along k:
+    c_s^2 G_s1 |k| - (c_s^4 / 2) G_s2 |k|^3 (Eq. (17))."""
+    g1, g2 = theory.effective_couplings(Ga, Gr)
+    return CS2 * g1 * k - 0.5 * CS2 * CS2 * g2 * k ** 3
+
+
+@pytest.mark.parametrize("direction", ["x", "y", "diag"])
+def test_long_wavelength_force(direction):
+    """Sinusoidal psi_A (self force, G_AB = 0) and rho_B (cross force alone):
+    the lattice force matches the two-term expansion to O(k^5)."""
+    N = 128
+    Ga, Gr, Gab, rho0 = -9.0, 8.1, 0.405, 0.83
+    yy, xx = np.mgrid[0:N, 0:N]
+    kv = {"x": (1, 0), "y": (0, 1), "diag": (1, 1)}[direction]
+    phase = 2 * np.pi * (kv[0] * xx + kv[1] * yy) / N
+    kmag = 2 * np.pi * math.hypot(*kv) / N
+    khat = np.array(kv) / math.hypot(*kv)
+    eps, psib, rhob = 1e-3, 0.4, 0.5
+    psiA = psib + eps * np.sin(phase)
+    rhoA = -rho0 * np.log(1 - psiA / rho0)          # invert Eq. (5)
+    rhoB = rhob + eps * np.sin(phase)
+    rho = np.stack([rhoA, rhoB])
+    # self force only
+    p = oracle.Params(nx=N, ny=N, tau=(1.0, 1.0), rho0=rho0, Ga=(Ga, Ga), Gr=(Gr, Gr), Gab=0.0)
+    F = oracle.force(p, rho)
+    exp_self = -psiA * eps * np.cos(phase) * _symbol(Ga, Gr, kmag)
+    scale = np.abs(exp_self).max()
+    for a in range(2):
+        assert np.abs(F[0, a] - exp_self * khat[a]).max() < 1e-5 * scale, a
+    # the G_s2 term is resolved: the one-term expansion misses by far more
+    g1 = theory.effective_couplings(Ga, Gr)[0]
+    one_term = -psiA * eps * np.cos(phase) * CS2 * g1 * kmag
+    along = F[0, 0] * khat[0] + F[0, 1] * khat[1]
+    assert np.abs(along - one_term).max() > 1e-3 * scale
+    # cross force only, acting on A through rho_B
+    p = oracle.Params(nx=N, ny=N, tau=(1.0, 1.0), rho0=rho0, Ga=(0, 0), Gr=(0, 0), Gab=Gab)
+    F = oracle.force(p, rho)
+    exp_x = -(Gab / rho0 ** 2) * rhoA * eps * np.cos(phase) * (CS2 * kmag - 0.5 * CS2 * CS2 * kmag ** 3)
+    scale = np.abs(exp_x).max()
+    for a in range(2):
+        assert np.abs(F[0, a] - exp_x * khat[a]).max() < 1e-5 * scale, a
+
+
+@pytest.mark.parametrize("taus,fracA", [((1.0, 1.0), 0.5), ((0.8, 0.8), 0.5), ((0.7, 1.3), 0.7)])
+def test_shear_wave_viscosity(taus, fracA):
+    N, T, U = 32, 400, 1e-4
+    p = oracle.Params(nx=4, ny=N, tau=taus, rho0=1.0, Ga=(0, 0), Gr=(0, 0), Gab=0.0)
+    y = np.arange(N)
+    ux = np.repeat((U * np.sin(2 * np.pi * y / N))[:, None], 4, axis=1)
+    f = oracle.init_equilibrium(p, np.full((N, 4), fracA), np.full((N, 4), 1 - fracA), ux, 0 * ux)
+    g, _ = oracle.run(p, f, T)
+    u = oracle.fields(p, g)["uphys"][0, :, 0]
+    amp = 2 * np.mean(u * np.sin(2 * np.pi * y / N))
+    k = 2 * np.pi / N
+    nu_meas = -math.log(amp / U) / T / k ** 2
+    taubar = fracA * taus[0] + (1 - fracA) * taus[1]      # Sec. III footnote
+    assert nu_meas == pytest.approx(CS2 * (taubar - 0.5), rel=0.015)
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.8])
+def test_couette_profile_and_wall_stress(tau):
+    ny, nx, U, T, avg = 16, 5, 0.01, 20000, 1000
+    p = oracle.Params(nx=nx, ny=ny, tau=(tau, tau), rho0=1.0, Ga=(0, 0), Gr=(0, 0), Gab=0.0,
+                      walls=True, u_wall=U)
+    f = oracle.init_equilibrium(p, np.full((ny, nx), 0.6), np.full((ny, nx), 0.4))
+    g, wm = oracle.run(p, f, T, avg_from=T - avg)
+    u = oracle.fields(p, g)["uphys"]
+    y = np.arange(ny)
+    expected = U * (2 * (y + 0.5) / ny - 1)             # walls at y = -1/2 and ny - 1/2
+    assert np.abs(u[0] - expected[:, None]).max() < 1e-13
+    assert np.abs(u[1]).max() < 1e-15
+    nu = CS2 * (tau - 0.5)
+    stress = 1.0 * nu * 2 * U / ny                      # rho nu du/dy, rho = 1
+    per_step = wm / avg / nx
+    assert per_step[1] == pytest.approx(-stress, rel=1e-9)   # fluid drags the top wall back
+    assert per_step[0] == pytest.approx(stress, rel=1e-9)
+
+
+@pytest.mark.parametrize("tau", [1.116071, 0.8])
+def test_pure_repulsion_bulk_densities(tau):
+    """Flat A-rich slab in B with only the cross force: the bulk densities
+    settle near Eq. (30) with rho_g^(tau) = theta(tau)/g_AB = 1.6."""
+    rho_g, rho_mean, n = 1.6, 3.5, 96
+    gab = theory.theta(tau) / rho_g
+    p = oracle.Params(nx=n, ny=5, tau=(tau, tau), rho0=1.0, Ga=(0, 0), Gr=(0, 0), Gab=gab)
+    hi, lo = theory.fixing_bulk_densities(rho_mean, rho_g)
+    x = np.arange(n)
+    inside = (x >= n // 4) & (x < 3 * n // 4)
+    ra = np.repeat(np.where(inside, hi, lo)[None, :], 5, axis=0)
+    rb = np.repeat(np.where(inside, lo, hi)[None, :], 5, axis=0)
+    g, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 6000)
+    r = oracle.density(p, g)
+    assert r[0, 2, n // 2] == pytest.approx(hi, rel=0.03)
+    assert r[1, 2, n // 2] == pytest.approx(lo, rel=0.03)
+    assert r[0, 2, 0] == pytest.approx(lo, rel=0.03)
+
+
+def test_pure_repulsion_mixed_below_threshold():
+    """Below <rho> = 2 rho_g^(tau) the mixed state is the only bulk solution of
+    Eq. (30): a noisy mixture relaxes back to uniform.  Above it, it separates."""
+    tau, rho_g = 1.0, 1.6
+    gab = theory.theta(tau) / rho_g
+    p = oracle.Params(nx=32, ny=32, tau=(tau, tau), rho0=1.0, Ga=(0, 0), Gr=(0, 0), Gab=gab)
+    for rho_mean, separates in ((2.6, False), (4.2, True)):
+        ra, rb = inputs.noise_fields(32, 32, 13, rho_mean / 2, rho_mean / 2, 0.01)
+        g, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 3000)
+        spread = np.ptp(oracle.density(p, g)[0])
+        assert (spread > 0.5) == separates, (rho_mean, spread)
+        if not separates:
+            assert spread < 0.02 * 0.1
