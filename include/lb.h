@@ -1,0 +1,170 @@
+/*
+ * lb.h -- C ABI of liblbsoft, an MI355X (gfx950) implementation of the time
+ * step of the two-species lattice Boltzmann model for soft-glassy fluids of
+ * Benzi, Sbragaglia, Succi, Bernaschi and Chibbaro (arXiv:0906.3611).
+ *
+ * One step (Sec. II) advances the populations f_is of species s in {A, B}
+ * on the D2Q9 lattice:
+ *   1. rho_s = sum_i f_is and psi_s = rho0 (1 - exp(-rho_s / rho0))   (Eq. (5))
+ *   2. Shan-Chen forces F_s (Eq. (2), weights of Table I): intra-species
+ *      attraction G^a_s on the first belt, repulsion G^r_s on both belts
+ *      (24 neighbours), A-B repulsion G_AB / rho0^2 on the first belt
+ *   3. common velocity u' = sum_s j_s / tau_s / sum_s rho_s / tau_s and
+ *      shifted velocities v_s = u' + tau_s F_s / rho_s                 (Eq. (1))
+ *   4. BGK relaxation of each species to the second-order equilibrium at
+ *      (rho_s, v_s), then free streaming                              (Eq. (1))
+ * on a periodic lattice, or with halfway bounce-back walls moving at -u_wall
+ * (below row 0) and +u_wall (above row ny-1) and x periodic.
+ *
+ * Conventions for every function below:
+ *  - Return value: LB_OK (0) or a negative LB_E_* status.  No function
+ *    aborts, exits or throws; the text of the last failure on a handle is
+ *    available from lb_last_error().
+ *  - Host arrays are FP64, row-major [ny][nx] with x fastest, whatever the
+ *    storage precision, and are only borrowed for the duration of the call.
+ *  - Work is enqueued on the HIP stream given at creation (NULL: the null
+ *    stream).  lb_step() is asynchronous; a numerical instability detected on
+ *    the device (a non-finite or non-positive density) is reported as
+ *    LB_E_UNSTABLE by the next synchronizing call (lb_observables,
+ *    lb_get_fields, lb_get_populations, lb_sync).
+ *  - A handle is not thread-safe; distinct handles may be used from
+ *    different threads.
+ */
+#ifndef LBSOFT_LB_H
+#define LBSOFT_LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LB_ABI_VERSION 1
+
+enum {
+  LB_OK = 0,
+  LB_E_INVAL = -1,    /* invalid argument or parameter */
+  LB_E_NOMEM = -2,    /* device allocation failed / workspace too small / not admitted */
+  LB_E_DEVICE = -3,   /* HIP runtime error */
+  LB_E_UNSTABLE = -4, /* non-finite or non-positive density met on the device */
+  LB_E_STATE = -5     /* call out of order (e.g. lb_step before lb_init) */
+};
+
+enum { LB_PERIODIC = 0, LB_COUETTE_Y = 1 };
+enum { LB_FP64 = 0, LB_FP32_DEV = 1 };
+
+/* Model and storage parameters.  Constraints checked by lb_create():
+ * nx, ny >= 5 (the +-2 stencil must reach distinct sites); tau_s > 1/2;
+ * rho0 > 0; all couplings finite.  G_a / G_r / G_AB are G^a_s, G^r_s and
+ * G_AB of Sec. II, Eq. (2) (positive repels, negative attracts). */
+typedef struct {
+  int32_t nx, ny;
+  int32_t boundary;   /* LB_PERIODIC or LB_COUETTE_Y */
+  int32_t precision;  /* LB_FP64: populations stored and updated in FP64.
+                         LB_FP32_DEV: stored and updated in FP32 as deviations
+                         f_is - w_i rho_ref_s; reductions stay FP64. */
+  double tau[2];
+  double rho0;
+  double G_a[2];
+  double G_r[2];
+  double G_AB;
+  double u_wall;      /* wall x-speed for LB_COUETTE_Y (top +u_wall, bottom -u_wall) */
+  double rho_ref[2];  /* LB_FP32_DEV reference densities; <= 0 selects the
+                         lattice mean of the fields given to lb_init() */
+  void* device_buffer;   /* optional caller-owned device workspace (e.g. the
+                            storage of a torch uint8 tensor); NULL: the library
+                            allocates.  Must stay alive until lb_destroy(). */
+  size_t device_bytes;   /* size of device_buffer; >= lb_workspace_bytes() */
+} lb_params;
+
+/* Observables of the state at the current time t (FP64 device reductions in
+ * a fixed order, so they are reproducible bit for bit). */
+typedef struct {
+  int64_t step;          /* t */
+  double mass[2];        /* sum_r rho_s */
+  double mom[2];         /* sum_r sum_s j_s, j_s = sum_i f_is c_i */
+  double mom_phys[2];    /* sum_r (sum_s j_s + F/2), F = F_A + F_B at time t */
+  double pxy_kin;        /* sum_r sum_s sum_i f_is c_ix c_iy (Sec. III, Eq. (10)) */
+  double wall_stress[2]; /* x-momentum handed to the (bottom, top) wall per step
+                            and per unit wall length, averaged over the steps
+                            since the last lb_reset_averages() */
+  int64_t avg_count;     /* number of steps in that average */
+  int32_t flags;         /* bit 0: instability seen */
+  int32_t pad_;
+} lb_obs;
+
+typedef struct lb_lattice lb_lattice;
+
+/* Device bytes one lattice needs for these parameters (two population
+ * buffers plus reduction and wall scratch).  out must not be NULL. */
+int lb_workspace_bytes(const lb_params* p, size_t* out);
+
+/* Validate p, take (or allocate) the device workspace and bind the HIP
+ * stream (a hipStream_t, borrowed; NULL = null stream).  The current HIP
+ * device at this call owns the lattice.  *out is NULL on failure. */
+int lb_create(const lb_params* p, void* hip_stream, lb_lattice** out);
+
+/* Set the state at t = 0 to the equilibrium populations f_is = f^eq_i(rho_s, u)
+ * (the paper's initial state, Sec. VI, has u = 0).  rho_a, rho_b: host
+ * [ny][nx], finite and > 0 (else LB_E_INVAL).  ux, uy: host [ny][nx] or NULL
+ * for zero.  Resets t, the averages and the instability flag.  Synchronous. */
+int lb_init(lb_lattice* lat, const double* rho_a, const double* rho_b, const double* ux,
+            const double* uy);
+
+/* Same as lb_init with rho_s = mean_s + amp (2U - 1), U uniform in [0, 1)
+ * drawn on the device: U = (z >> 11) 2^-53 with z output number
+ * (s ny + y) nx + x + 1 of SplitMix64 seeded with seed.  Requires
+ * |amp| < min(mean_a, mean_b).  With LB_FP32_DEV and rho_ref <= 0 the
+ * reference densities are mean_a and mean_b. */
+int lb_init_noise(lb_lattice* lat, uint64_t seed, double mean_a, double mean_b, double amp);
+
+/* Enqueue n >= 0 time steps (Sec. II, Eq. (1)).  Asynchronous. */
+int lb_step(lb_lattice* lat, int64_t n);
+
+/* Observables of the current state (synchronizes). */
+int lb_observables(lb_lattice* lat, lb_obs* out);
+
+/* Fields of the current state into host arrays (each may be NULL):
+ * rho_a, rho_b [ny][nx]; u [2][ny][nx] the common velocity u'; u_phys
+ * [2][ny][nx] = (sum_s j_s + F/2) / (rho_A + rho_B).  Synchronizes. */
+int lb_get_fields(lb_lattice* lat, double* rho_a, double* rho_b, double* u, double* u_phys);
+
+/* Pre-collision populations f_is(r, t) of the current state into host
+ * f[2][9][ny][nx] (FP64, D2Q9 order rest, +x, +y, -x, -y, (1,1), (-1,1),
+ * (-1,-1), (1,-1)).  Synchronizes. */
+int lb_get_populations(lb_lattice* lat, double* f);
+
+/* Replace the current state by host populations f[2][9][ny][nx] (same
+ * layout) at time t = step (checkpoint restore).  For LB_FP32_DEV the
+ * deviations f - w_i rho_ref_s are rounded to FP32.  Resets the averages. */
+int lb_set_populations(lb_lattice* lat, const double* f, int64_t step);
+
+/* Restart the wall-stress average at the current step. */
+int lb_reset_averages(lb_lattice* lat);
+
+/* Wait for all enqueued work; reports LB_E_UNSTABLE if flagged. */
+int lb_sync(lb_lattice* lat);
+
+/* Current time step t (host counter; no synchronization). */
+int64_t lb_current_step(const lb_lattice* lat);
+
+/* How a step is launched: the lattice is cut into nstrips column strips of
+ * at most 60 columns and nsegs row segments; each (strip, segment) tile is
+ * one 64-lane wavefront (one workgroup), grid_blocks workgroups per step. */
+typedef struct {
+  int32_t nstrips, nsegs, ntiles, grid_blocks, block_threads, pitch;
+  size_t workspace_bytes;
+  size_t population_bytes;   /* one population buffer: 18 planes */
+} lb_launch_info;
+int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
+
+void lb_destroy(lb_lattice* lat);
+const char* lb_strerror(int status);
+const char* lb_last_error(const lb_lattice* lat);
+int lb_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBSOFT_LB_H */

@@ -1,0 +1,77 @@
+// Internal declarations shared by the kernels (lb_kernels.hip) and the
+// runtime behind the C ABI (lb_runtime.hip).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lbk {
+
+// One wavefront marches down a strip of kWave lattice columns.  The two
+// columns on each side are the stencil ring, so a strip updates kStrip
+// columns.  The density / pseudopotential rows of the 5-row stencil live in
+// a ring of kRing LDS rows.
+constexpr int kWave = 64;
+constexpr int kStrip = kWave - 4;
+constexpr int kRing = 5;
+
+enum Mode : int { kStep = 0, kObserve = 1 };
+
+// Number of FP64 values each wave writes in observe mode.
+constexpr int kNRed = 8;  // massA, massB, momx, momy, momphys_x, momphys_y, pxy, spare
+
+// Physical constants of one lattice, in FP64 (converted per kernel).
+struct Coefs {
+  // Self-force weights per species by class |c|^2 = 1, 2, 4, 5, 8:
+  // G^a w + G^r p on the first belt, G^r p on the second (Eq. (2), Table I).
+  double kself[2][5];
+  // Cross-force weights G_AB / rho0^2 * w for |c|^2 = 1, 2.
+  double kcross[2];
+  double rho0, inv_rho0;
+  double tau[2], omega[2];
+  double rho_ref[2];  // deviation references (deviation storage only)
+  double u_wall;      // +u_wall at the top wall, -u_wall at the bottom
+};
+
+struct Geometry {
+  int nx, ny, pitch;
+  long long plane;  // elements in one (species, direction) plane = pitch * ny
+  int nstrips, seg_h, nsegs, ntiles, tiles_per_xcd;
+};
+
+struct StepArgs {
+  const void* src;      // populations streamed into time t (pull layout)
+  void* dst;            // populations written for time t + 1
+  const void* wall_in;  // wall-link populations entering time t
+  void* wall_out;       // wall-link populations entering time t + 1
+  double* wave_red;     // observe: kNRed values per tile
+  double* wave_wall;    // step: 2 accumulators (bottom, top) per tile
+  double* fields;       // observe: [6][ny][nx] or null
+  double* pops;         // observe: [2][9][ny][nx] or null
+  int* flag;            // bit 0 set when a density is non-finite or <= 0
+  int accumulate_wall;  // step: add wall momentum to wave_wall
+  Geometry g;
+  Coefs c;
+};
+
+// Launchers (lb_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, hipStream_t st);
+hipError_t launch_observe(const StepArgs& a, bool fp64, bool walls, hipStream_t st);
+// Fixed-order sum of ntiles * width per-tile values into out[width].
+hipError_t launch_reduce_tiles(const double* in, int ntiles, int width, double* out,
+                               hipStream_t st);
+// Write the t = 0 state: src buffer in pull layout plus the wall links, from
+// FP64 densities / velocities on the device (u may be null).
+hipError_t launch_init(const Geometry& g, const Coefs& c, bool fp64, bool walls,
+                       const double* rho /*[2][ny][nx]*/, const double* u /*[2][ny][nx]*/,
+                       void* buf, void* wall, hipStream_t st);
+// Same from host-supplied populations f[2][9][ny][nx] (device copy).
+hipError_t launch_set_pops(const Geometry& g, const Coefs& c, bool fp64, bool walls,
+                           const double* f, void* buf, void* wall, hipStream_t st);
+// Counter-based noise densities rho_s = mean_s + amp (2U - 1) into rho[2][ny][nx].
+hipError_t launch_noise(int nx, int ny, uint64_t seed, double mean_a, double mean_b, double amp,
+                        double* rho, hipStream_t st);
+
+}  // namespace lbk

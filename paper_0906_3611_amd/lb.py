@@ -1,0 +1,240 @@
+"""Python binding of liblbsoft (include/lb.h): argument marshalling only.
+
+Every step of the lattice Boltzmann update runs in the library's HIP
+kernels.  PyTorch supplies the device workspace (a uint8 CUDA tensor) and
+the HIP stream (torch's current stream), so library work interleaves with
+torch work and torch's events can time it.  If the compiled library is
+missing this module raises at import-time use; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbsoft.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "lb.h")
+
+LB_OK, LB_E_INVAL, LB_E_NOMEM, LB_E_DEVICE, LB_E_UNSTABLE, LB_E_STATE = 0, -1, -2, -3, -4, -5
+LB_PERIODIC, LB_COUETTE_Y = 0, 1
+LB_FP64, LB_FP32_DEV = 0, 1
+
+
+class LBError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class lb_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("boundary", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("tau", ctypes.c_double * 2), ("rho0", ctypes.c_double),
+                ("G_a", ctypes.c_double * 2), ("G_r", ctypes.c_double * 2), ("G_AB", ctypes.c_double),
+                ("u_wall", ctypes.c_double), ("rho_ref", ctypes.c_double * 2),
+                ("device_buffer", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t)]
+
+
+class lb_obs(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("mass", ctypes.c_double * 2), ("mom", ctypes.c_double * 2),
+                ("mom_phys", ctypes.c_double * 2), ("pxy_kin", ctypes.c_double),
+                ("wall_stress", ctypes.c_double * 2), ("avg_count", ctypes.c_int64),
+                ("flags", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class lb_launch_info(ctypes.Structure):
+    _fields_ = [("nstrips", ctypes.c_int32), ("nsegs", ctypes.c_int32), ("ntiles", ctypes.c_int32),
+                ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
+                ("population_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load():
+    """Load liblbsoft.so (built by __graft_entry__.build()).  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: the HIP library has not been built "
+                          "(run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    vp, dp, i64 = ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64
+    lat = ctypes.c_void_p
+    sig = {
+        "lb_abi_version": ([], ctypes.c_int),
+        "lb_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "lb_last_error": ([lat], ctypes.c_char_p),
+        "lb_workspace_bytes": ([P(lb_params), P(ctypes.c_size_t)], ctypes.c_int),
+        "lb_create": ([P(lb_params), vp, P(lat)], ctypes.c_int),
+        "lb_init": ([lat, dp, dp, dp, dp], ctypes.c_int),
+        "lb_init_noise": ([lat, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+                          ctypes.c_int),
+        "lb_step": ([lat, i64], ctypes.c_int),
+        "lb_observables": ([lat, P(lb_obs)], ctypes.c_int),
+        "lb_get_fields": ([lat, dp, dp, dp, dp], ctypes.c_int),
+        "lb_get_populations": ([lat, dp], ctypes.c_int),
+        "lb_set_populations": ([lat, dp, i64], ctypes.c_int),
+        "lb_reset_averages": ([lat], ctypes.c_int),
+        "lb_sync": ([lat], ctypes.c_int),
+        "lb_current_step": ([lat], i64),
+        "lb_get_launch_info": ([lat, P(lb_launch_info)], ctypes.c_int),
+        "lb_destroy": ([lat], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/lb.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_]+)\s*\(", txt)))
+
+
+def _dptr(a):
+    if a is None:
+        return ctypes.cast(None, ctypes.POINTER(ctypes.c_double))
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+class Lattice:
+    """One two-species lattice on the current GPU.
+
+    precision: "fp64" or "fp32dev"; boundary: "periodic" or "couette".
+    With use_torch (default) the device workspace is a torch uint8 tensor and
+    work runs on torch's current stream; otherwise the library allocates and
+    uses the null stream.
+    """
+
+    def __init__(self, nx: int, ny: int, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0),
+                 G_r=(8.1, 8.1), G_AB=0.405, boundary="periodic", u_wall=0.0, precision="fp64",
+                 rho_ref=(0.0, 0.0), use_torch=True, stream=None):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        self.nx, self.ny = int(nx), int(ny)
+        p = lb_params()
+        p.nx, p.ny = self.nx, self.ny
+        p.boundary = {"periodic": LB_PERIODIC, "couette": LB_COUETTE_Y}[boundary]
+        p.precision = {"fp64": LB_FP64, "fp32dev": LB_FP32_DEV}[precision]
+        p.tau[0], p.tau[1] = tau
+        p.rho0 = rho0
+        p.G_a[0], p.G_a[1] = G_a
+        p.G_r[0], p.G_r[1] = G_r
+        p.G_AB = G_AB
+        p.u_wall = u_wall
+        p.rho_ref[0], p.rho_ref[1] = rho_ref
+        self.precision, self.boundary = precision, boundary
+        nbytes = ctypes.c_size_t()
+        self._check(self._lib.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)), "workspace")
+        self._buf = None
+        sptr = None
+        if use_torch:
+            import torch
+            self._buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
+            p.device_buffer = self._buf.data_ptr()
+            p.device_bytes = int(nbytes.value)
+            self.stream = torch.cuda.current_stream() if stream is None else stream
+            sptr = self.stream.cuda_stream
+        else:
+            self.stream = stream
+            sptr = None if stream is None else int(stream)
+        self._check(self._lib.lb_create(ctypes.byref(p), sptr, ctypes.byref(self._h)), "lb_create")
+        self.params = p
+
+    # -- plumbing ---------------------------------------------------------
+    def _check(self, rc, what):
+        if rc != LB_OK:
+            msg = ""
+            if getattr(self, "_h", None) and self._h.value:
+                msg = (self._lib.lb_last_error(self._h) or b"").decode()
+            raise LBError(rc, f"{what}: {self._lib.lb_strerror(rc).decode()}: {msg}")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.lb_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self._buf = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- API ----------------------------------------------------------------
+    def init(self, rho_a, rho_b, ux=None, uy=None):
+        shp = (self.ny, self.nx)
+        ra, rb = _f64(rho_a, shp), _f64(rho_b, shp)
+        vx = None if ux is None else _f64(ux, shp)
+        vy = None if uy is None else _f64(uy, shp)
+        self._check(self._lib.lb_init(self._h, _dptr(ra), _dptr(rb), _dptr(vx), _dptr(vy)), "lb_init")
+
+    def init_noise(self, seed, mean_a, mean_b, amp):
+        self._check(self._lib.lb_init_noise(self._h, int(seed), float(mean_a), float(mean_b),
+                                            float(amp)), "lb_init_noise")
+
+    def step(self, n=1):
+        self._check(self._lib.lb_step(self._h, int(n)), "lb_step")
+
+    @property
+    def t(self) -> int:
+        return int(self._lib.lb_current_step(self._h))
+
+    def observables(self) -> dict:
+        o = lb_obs()
+        self._check(self._lib.lb_observables(self._h, ctypes.byref(o)), "lb_observables")
+        return {"step": o.step, "mass": np.array(o.mass[:]), "mom": np.array(o.mom[:]),
+                "mom_phys": np.array(o.mom_phys[:]), "pxy_kin": o.pxy_kin,
+                "wall_stress": np.array(o.wall_stress[:]), "avg_count": o.avg_count,
+                "flags": o.flags}
+
+    def fields(self) -> dict:
+        ny, nx = self.ny, self.nx
+        ra, rb = np.empty((ny, nx)), np.empty((ny, nx))
+        u, up = np.empty((2, ny, nx)), np.empty((2, ny, nx))
+        self._check(self._lib.lb_get_fields(self._h, _dptr(ra), _dptr(rb), _dptr(u), _dptr(up)),
+                    "lb_get_fields")
+        return {"rho": np.stack([ra, rb]), "u": u, "uphys": up}
+
+    def populations(self) -> np.ndarray:
+        f = np.empty((2, 9, self.ny, self.nx))
+        self._check(self._lib.lb_get_populations(self._h, _dptr(f)), "lb_get_populations")
+        return f
+
+    def set_populations(self, f, step=0):
+        f = _f64(f, (2, 9, self.ny, self.nx))
+        self._check(self._lib.lb_set_populations(self._h, _dptr(f), int(step)), "lb_set_populations")
+
+    def reset_averages(self):
+        self._check(self._lib.lb_reset_averages(self._h), "lb_reset_averages")
+
+    def sync(self):
+        self._check(self._lib.lb_sync(self._h), "lb_sync")
+
+    def launch_info(self) -> dict:
+        li = lb_launch_info()
+        self._check(self._lib.lb_get_launch_info(self._h, ctypes.byref(li)), "lb_get_launch_info")
+        return {k: getattr(li, k) for k, _ in lb_launch_info._fields_}

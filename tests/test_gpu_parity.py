@@ -1,0 +1,253 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances.  FP64 storage: the GPU and the oracle differ only in rounding
+order (FMA contraction, exp, summation order), ~1e-16 per step; C1's
+pattern-forming dynamics amplify a 1-ulp perturbation of the initial state
+to ~1e-12 after 2000 steps (twin experiment), so fields must agree to
+max(1e-10, 100 x twin) = 1e-10 there and to 1e-13 over short runs.
+FP32 deviation storage: per-step rounding of the stored deviations is
+~6e-8 relative; over short runs, and in regimes that do not amplify it,
+fields agree to 2e-6 absolute; for C1 over long runs the error is compared
+with the oracle's own FP32-rounding twin envelope.
+"""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (first import can be slow; keep it out of test timeouts)
+
+import oracle
+from paper_0906_3611_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+C1 = dict(tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405)
+
+
+def _lb():
+    from paper_0906_3611_amd import lb
+    return lb
+
+
+def oparams(nx, ny, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405,
+            boundary="periodic", u_wall=0.0):
+    return oracle.Params(nx=nx, ny=ny, tau=tau, rho0=rho0, Ga=G_a, Gr=G_r, Gab=G_AB,
+                         walls=(boundary == "couette"), u_wall=u_wall)
+
+
+def make(nx, ny, precision="fp64", boundary="periodic", u_wall=0.0, rho_ref=(0.0, 0.0), **kw):
+    par = dict(C1)
+    par.update(kw)
+    lat = _lb().Lattice(nx, ny, precision=precision, boundary=boundary, u_wall=u_wall,
+                        rho_ref=rho_ref, **par)
+    return lat, oparams(nx, ny, boundary=boundary, u_wall=u_wall, **par)
+
+
+def noise(nx, ny, seed=1, mean=0.5, amp=0.01):
+    return inputs.noise_fields(nx, ny, seed, mean, mean, amp)
+
+
+def test_init_matches_oracle_equilibrium():
+    lat, p = make(67, 61)
+    ra, rb = noise(67, 61, seed=3)
+    lat.init(ra, rb)
+    f_ref = oracle.init_equilibrium(p, ra, rb)
+    assert np.abs(lat.populations() - f_ref).max() < 1e-16
+    fl = lat.fields()
+    assert np.array_equal(fl["rho"][0], oracle.density(p, f_ref)[0]) or \
+        np.abs(fl["rho"] - oracle.density(p, f_ref)).max() < 1e-15
+
+
+def test_device_noise_matches_host_generator():
+    lat, p = make(67, 61)
+    lat.init_noise(5, 0.5, 0.45, 0.01)
+    ra, rb = inputs.noise_fields(67, 61, 5, 0.5, 0.45, 0.01)
+    f_ref = oracle.init_equilibrium(p, ra, rb)
+    assert np.abs(lat.populations() - f_ref).max() < 1e-16
+
+
+@pytest.mark.parametrize("nx,ny", [(67, 61), (5, 5), (130, 7), (61, 64), (121, 9), (64, 64)])
+@pytest.mark.parametrize("boundary", ["periodic", "couette"])
+def test_fp64_short_run_ragged_sizes(nx, ny, boundary):
+    u_wall = 0.02 if boundary == "couette" else 0.0
+    lat, p = make(nx, ny, boundary=boundary, u_wall=u_wall)
+    ra, rb = noise(nx, ny, seed=nx * 1000 + ny, amp=0.05)
+    lat.init(ra, rb)
+    f = oracle.init_equilibrium(p, ra, rb)
+    done = 0
+    for k in (1, 4, 20):
+        lat.step(k - done)
+        f, _ = oracle.run(p, f, k - done)
+        done = k
+        err = np.abs(lat.populations() - f).max()
+        assert err < 1e-13, (nx, ny, boundary, k, err)
+
+
+def test_fp64_c1_parity_2000_steps():
+    """C1: 64x64 periodic, rho = 0.5 +- 0.01, standard rho0 = 0.83 couplings."""
+    lat, p = make(64, 64)
+    ra, rb = noise(64, 64, seed=1)
+    lat.init(ra, rb)
+    f = oracle.init_equilibrium(p, ra, rb)
+    done = 0
+    for k, tol in ((1, 1e-14), (10, 1e-14), (100, 1e-13), (2000, 1e-10)):
+        lat.step(k - done)
+        f, _ = oracle.run(p, f, k - done)
+        done = k
+        fl = lat.fields()
+        ref = oracle.fields(p, f)
+        err_rho = np.abs(fl["rho"] - ref["rho"]).max()
+        err_u = np.abs(fl["uphys"] - ref["uphys"]).max()
+        err_u2 = np.abs(fl["u"] - ref["u"]).max()
+        assert err_rho < tol and err_u < tol and err_u2 < tol, (k, err_rho, err_u, err_u2)
+    obs = lat.observables()
+    tot = oracle.totals(p, f)
+    assert np.allclose(obs["mass"], tot["mass"], rtol=1e-14, atol=0)
+    assert np.abs(obs["mom"] - tot["mom"]).max() < 1e-11
+    assert abs(obs["pxy_kin"] - tot["pxy_kin"]) < 1e-10
+
+
+def test_fp64_couette_with_forces_and_wall_stress():
+    nx, ny, U = 40, 24, 0.02
+    lat, p = make(nx, ny, boundary="couette", u_wall=U)
+    ra, rb = noise(nx, ny, seed=8, amp=0.02)
+    lat.init(ra, rb)
+    lat.step(50)
+    lat.reset_averages()
+    lat.step(100)
+    f, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 50)
+    f, wm = oracle.run(p, f, 100, avg_from=0)
+    assert np.abs(lat.populations() - f).max() < 1e-13
+    obs = lat.observables()
+    assert obs["avg_count"] == 100
+    assert np.allclose(obs["wall_stress"], wm / 100 / nx, rtol=1e-11, atol=1e-17)
+    assert np.allclose(obs["mass"], oracle.totals(p, f)["mass"], rtol=1e-14)
+
+
+def test_fp32dev_short_runs():
+    for boundary in ("periodic", "couette"):
+        nx, ny = 67, 40
+        u_wall = 0.01 if boundary == "couette" else 0.0
+        lat, p = make(nx, ny, precision="fp32dev", boundary=boundary, u_wall=u_wall)
+        ra, rb = noise(nx, ny, seed=2)
+        lat.init(ra, rb)
+        lat.step(100)
+        f, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 100)
+        fl = lat.fields()
+        ref = oracle.fields(p, f)
+        assert np.abs(fl["rho"] - ref["rho"]).max() < 2e-6, boundary
+        assert np.abs(fl["uphys"] - ref["uphys"]).max() < 2e-6, boundary
+
+
+def test_fp32dev_c1_within_twin_envelope():
+    """Over 2000 C1 steps rounding is amplified by the demixing instability;
+    the FP32 path must stay within 10x the envelope the oracle itself shows
+    when its initial state is rounded to FP32 (one FP32 rounding)."""
+    lat, p = make(64, 64, precision="fp32dev")
+    ra, rb = noise(64, 64, seed=1)
+    lat.init(ra, rb)
+    f0 = oracle.init_equilibrium(p, ra, rb)
+    twin0 = f0.astype(np.float32).astype(np.float64)
+    lat.step(2000)
+    f, _ = oracle.run(p, f0, 2000)
+    t, _ = oracle.run(p, twin0, 2000)
+    env = np.abs(oracle.density(p, t) - oracle.density(p, f)).max()
+    err = np.abs(lat.fields()["rho"] - oracle.density(p, f)).max()
+    assert err < max(10 * env, 1e-6), (err, env)
+    m = lat.observables()["mass"]
+    assert np.allclose(m, oracle.totals(p, f0)["mass"], rtol=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_translation_equivariance_bitwise(precision):
+    nx, ny = 70, 45
+    ra, rb = noise(nx, ny, seed=4, amp=0.05)
+    dx, dy = 13, 7
+    outs = []
+    for sh in ((0, 0), (dx, dy)):
+        lat, _ = make(nx, ny, precision=precision, rho_ref=(0.5, 0.5))
+        lat.init(np.roll(ra, sh, axis=(0, 1)) if sh != (0, 0) else ra,
+                 np.roll(rb, sh, axis=(0, 1)) if sh != (0, 0) else rb)
+        lat.step(30)
+        outs.append(lat.populations())
+    # shift (dy, dx) applied to rows, cols
+    a = np.roll(outs[0], (dx, dy), axis=(2, 3))
+    assert np.array_equal(a, outs[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_deterministic_and_resumable(precision):
+    nx, ny = 61, 33
+    ra, rb = noise(nx, ny, seed=6, amp=0.05)
+    runs = []
+    for _ in range(2):
+        lat, _ = make(nx, ny, precision=precision)
+        lat.init(ra, rb)
+        lat.step(25)
+        runs.append(lat)
+    f1, f2 = runs[0].populations(), runs[1].populations()
+    assert np.array_equal(f1, f2)
+    o1, o2 = runs[0].observables(), runs[1].observables()
+    assert np.array_equal(o1["mass"], o2["mass"]) and o1["pxy_kin"] == o2["pxy_kin"]
+    # resume: restore the state at t = 25 into the first lattice and continue
+    runs[1].step(15)
+    runs[0].set_populations(f1, step=25)
+    runs[0].step(15)
+    assert runs[0].t == 40
+    assert np.array_equal(runs[0].populations(), runs[1].populations())
+
+
+def test_species_swap_symmetry():
+    nx, ny = 40, 30
+    ra, rb = noise(nx, ny, seed=12, amp=0.05)
+    a, _ = make(nx, ny)
+    b, _ = make(nx, ny)
+    a.init(ra, rb)
+    b.init(rb, ra)
+    a.step(40)
+    b.step(40)
+    fa, fb = a.populations(), b.populations()
+    assert np.abs(fa[::-1] - fb).max() < 1e-14
+
+
+def test_full_size_c2_sampled_fp64_and_fp32dev():
+    """C2 shape (1024^2 periodic, disc emulsion at phi = 0.7): 3 steps on the
+    GPU in the benchmark's launch configuration against the full oracle."""
+    nx = ny = 1024
+    ra, rb = inputs.disc_fields(nx, ny, 2, 0.7)
+    p = oparams(nx, ny, **C1)
+    f, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 3)
+    ref = oracle.fields(p, f)
+    for precision, tol in (("fp64", 1e-13), ("fp32dev", 2e-6)):
+        lat, _ = make(nx, ny, precision=precision)
+        lat.init(ra, rb)
+        lat.step(3)
+        fl = lat.fields()
+        assert np.abs(fl["rho"] - ref["rho"]).max() < tol, precision
+        assert np.abs(fl["uphys"] - ref["uphys"]).max() < tol, precision
+        lat.close()
+
+
+def test_instability_is_reported():
+    """A state driven far from equilibrium makes densities negative; the next
+    synchronizing call reports LB_E_UNSTABLE instead of returning garbage."""
+    lb = _lb()
+    lat = lb.Lattice(16, 16, tau=(0.51, 0.51), rho0=0.83, G_a=(-400.0, -400.0), G_r=(0.0, 0.0),
+                     G_AB=50.0)
+    ra, rb = noise(16, 16, seed=1, mean=0.5, amp=0.4)
+    lat.init(ra, rb)
+    lat.step(200)
+    with pytest.raises(lb.LBError) as ei:
+        lat.sync()
+    assert ei.value.code == lb.LB_E_UNSTABLE
+
+
+def test_invalid_init_rejected():
+    lb = _lb()
+    lat, _ = make(16, 16)
+    ra, rb = noise(16, 16)
+    ra[3, 4] = -0.1
+    with pytest.raises(lb.LBError) as ei:
+        lat.init(ra, rb)
+    assert ei.value.code == lb.LB_E_INVAL
+    with pytest.raises(lb.LBError) as ei:
+        lat.step(1)
+    assert ei.value.code == lb.LB_E_STATE
