@@ -150,7 +150,7 @@ int lb_sync(lb_lattice* lat);
 int64_t lb_current_step(const lb_lattice* lat);
 
 /* How a step is launched: the lattice is cut into nstrips column strips of
- * at most 60 columns and nsegs row segments; each (strip, segment) tile is
+ * at most 64 columns and nsegs row segments; each (strip, segment) tile is
  * one 64-lane wavefront (one workgroup), grid_blocks workgroups per step. */
 typedef struct {
   int32_t nstrips, nsegs, ntiles, grid_blocks, block_threads, pitch;

@@ -9,12 +9,10 @@
 
 namespace lbk {
 
-// One wavefront marches down a strip of kWave lattice columns.  The two
-// columns on each side are the stencil ring, so a strip updates kStrip
-// columns.  The density / pseudopotential rows of the 5-row stencil live in
-// a ring of kRing LDS rows.
+// One wavefront marches along a strip of kWave lattice columns (plus a
+// 2-column stencil ring on each side).  The density / pseudopotential rows
+// of the 5-row stencil live in a ring of kRing LDS rows.
 constexpr int kWave = 64;
-constexpr int kStrip = kWave - 4;
 constexpr int kRing = 5;
 
 enum Mode : int { kStep = 0, kObserve = 1 };
@@ -31,8 +29,14 @@ struct Coefs {
   double kcross[2];
   double rho0, inv_rho0;
   double tau[2], omega[2];
-  double rho_ref[2];  // deviation references (deviation storage only)
+  double rho_ref[2];  // deviation references (deviation storage only; FP32-representable)
+  double psi_ref[2];  // psi(rho_ref)
+  double psi_scale[2];  // rho0 exp(-rho_ref / rho0): psi(rho_ref + d) - psi_ref = -psi_scale expm1(-d / rho0)
   double u_wall;      // +u_wall at the top wall, -u_wall at the bottom
+  // The same constants rounded to FP32 on the host, so FP32 kernels read
+  // them straight into scalar registers.
+  float f_kself[2][5], f_kcross[2], f_rho0, f_inv_rho0, f_tau[2], f_omega[2], f_rho_ref[2],
+      f_psi_ref[2], f_psi_scale[2], f_u_wall;
 };
 
 struct Geometry {
@@ -57,7 +61,8 @@ struct StepArgs {
 };
 
 // Launchers (lb_kernels.hip).  All return hipError_t of the launch.
-hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, hipStream_t st);
+// prefetch: issue the next row's pull before the current collision.
+hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, int prefetch, hipStream_t st);
 hipError_t launch_observe(const StepArgs& a, bool fp64, bool walls, hipStream_t st);
 // Fixed-order sum of ntiles * width per-tile values into out[width].
 hipError_t launch_reduce_tiles(const double* in, int ntiles, int width, double* out,

@@ -9,18 +9,19 @@
 // wall are kept in a small side buffer [wall][s][link][nx], written by the
 // collision that sends them out.
 //
-// Decomposition.  One 64-lane wavefront owns a strip of at most 60 columns
-// plus a 2-column ring on each side, and marches down a segment of rows.
-// For every row it pulls the 18 populations (2 species x 9 directions) of
-// its 64 columns, forms rho_s and psi_s into a 5-row LDS ring, and collides
-// the row two behind, whose 25-point stencil is then complete.  Interior
-// rows keep their pulled populations in registers until their collision, so
-// every population is read from HBM once per step apart from the ring
-// re-reads, which the neighbouring strips have just brought into L2.
+// Decomposition.  One 64-lane wavefront owns a line-aligned strip of 64
+// columns and marches along a segment of rows.  For every row it pulls the
+// 18 populations (2 species x 9 directions) of its columns and of the two
+// ring columns on each side, forms rho_s and psi_s into a 5-row LDS ring,
+// and collides the row two behind, whose 25-point stencil is then complete.
+// Pulled populations stay in registers until their collision, so every
+// population is read from HBM once per step apart from the ring re-reads,
+// which neighbouring strips and segments bring into L2 at the same time.
 #include "lb_internal.h"
 
 #include <cmath>
 #include <type_traits>
+#include <utility>
 
 namespace lbk {
 namespace {
@@ -58,6 +59,12 @@ template <>
 __device__ __forceinline__ float exp_ct<float>(float x) { return expf(x); }
 template <>
 __device__ __forceinline__ double exp_ct<double>(double x) { return exp(x); }
+template <typename CT>
+__device__ __forceinline__ CT expm1_ct(CT x);
+template <>
+__device__ __forceinline__ float expm1_ct<float>(float x) { return expm1f(x); }
+template <>
+__device__ __forceinline__ double expm1_ct<double>(double x) { return expm1(x); }
 
 // Ordering point for LDS traffic of a single-wave workgroup: every earlier
 // LDS access has completed and no access moves across it.
@@ -69,69 +76,124 @@ __device__ __forceinline__ int wrap(int v, int n) {
 }
 
 template <typename CT, bool DEV>
-struct Params {
-  CT k[2][5];
-  CT kx[2];
-  CT rho0, inv_rho0, tau[2], om[2], rref[2], uw;
+struct Params;
+
+template <bool DEV>
+struct Params<double, DEV> {
+  double k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw;
   __device__ explicit Params(const Coefs& c) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
-      for (int m = 0; m < 5; ++m) k[s][m] = (CT)c.kself[s][m];
-      tau[s] = (CT)c.tau[s];
-      om[s] = (CT)c.omega[s];
-      rref[s] = DEV ? (CT)c.rho_ref[s] : CT(0);
+      for (int m = 0; m < 5; ++m) k[s][m] = c.kself[s][m];
+      tau[s] = c.tau[s];
+      om[s] = c.omega[s];
+      rref[s] = DEV ? c.rho_ref[s] : 0.0;
+      pref[s] = DEV ? c.psi_ref[s] : 0.0;
+      pscale[s] = c.psi_scale[s];
     }
-    kx[0] = (CT)c.kcross[0];
-    kx[1] = (CT)c.kcross[1];
-    rho0 = (CT)c.rho0;
-    inv_rho0 = (CT)c.inv_rho0;
-    uw = (CT)c.u_wall;
+    kx[0] = c.kcross[0];
+    kx[1] = c.kcross[1];
+    rho0 = c.rho0;
+    inv_rho0 = c.inv_rho0;
+    uw = c.u_wall;
   }
 };
 
-// Pull the 18 populations streaming into row re (a lattice row) for the
-// wave's columns.  colm / colc / colp are the source columns for
-// c_x = +1 / 0 / -1.
-template <typename ST, typename CT, bool WALLS>
-__device__ __forceinline__ void pull_row(const StepArgs& a, const ST* __restrict__ src,
-                                         const ST* __restrict__ wall_in, int re, int colm,
-                                         int colc, int colp, CT (&f)[2][9]) {
-  const Geometry& g = a.g;
-  int rm, rp;  // source rows for c_y = +1 and c_y = -1
-  if (WALLS) {
-    rm = re > 0 ? re - 1 : 0;
-    rp = re < g.ny - 1 ? re + 1 : g.ny - 1;
-  } else {
-    rm = re > 0 ? re - 1 : g.ny - 1;
-    rp = re < g.ny - 1 ? re + 1 : 0;
+template <bool DEV>
+struct Params<float, DEV> {
+  float k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw;
+  __device__ explicit Params(const Coefs& c) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int m = 0; m < 5; ++m) k[s][m] = c.f_kself[s][m];
+      tau[s] = c.f_tau[s];
+      om[s] = c.f_omega[s];
+      rref[s] = DEV ? c.f_rho_ref[s] : 0.0f;
+      pref[s] = DEV ? c.f_psi_ref[s] : 0.0f;
+      pscale[s] = c.f_psi_scale[s];
+    }
+    kx[0] = c.f_kcross[0];
+    kx[1] = c.f_kcross[1];
+    rho0 = c.f_rho0;
+    inv_rho0 = c.f_inv_rho0;
+    uw = c.f_u_wall;
   }
-  const bool bottom = WALLS && re == 0;
-  const bool top = WALLS && re == g.ny - 1;
+};
+
+template <typename CT>
+__device__ __forceinline__ CT rcp_ct(CT x);
+template <>
+__device__ __forceinline__ float rcp_ct<float>(float x) {
+  // hardware reciprocal (1 ulp) refined by one Newton step
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+template <>
+__device__ __forceinline__ double rcp_ct<double>(double x) { return 1.0 / x; }
+
+// Loads and stores at a wave-uniform base plus a 32-bit per-lane byte
+// offset, so the address is an SGPR pair plus one VGPR (no 64-bit per-lane
+// address arithmetic).
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, uint32_t byte_off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)byte_off) = v;
+}
+
+// Source rows of a pull into lattice row re: rm for c_y = +1, rp for c_y = -1.
+template <bool WALLS>
+__device__ __forceinline__ void source_rows(int re, int ny, int& rm, int& rp) {
+  if (WALLS) {
+    rm = re > 0 ? re - 1 : 0;  // row 0's c_y = +1 links come from the wall buffer
+    rp = re < ny - 1 ? re + 1 : ny - 1;
+  } else {
+    rm = re > 0 ? re - 1 : ny - 1;
+    rp = re < ny - 1 ? re + 1 : 0;
+  }
+}
+
+// Pull the 18 populations streaming into row re at column col.  ob_m / ob_c
+// / ob_p are the byte offsets of the source columns col - 1, col, col + 1
+// (sources of c_x = +1, 0, -1).
+template <typename ST, typename CT, bool WALLS>
+__device__ __forceinline__ void pull(const Geometry& g, const ST* __restrict__ src,
+                                     const ST* __restrict__ wall_in, int re, uint32_t ob_m,
+                                     uint32_t ob_c, uint32_t ob_p, int col, CT (&f)[2][9]) {
+  int rm, rp;
+  source_rows<WALLS>(re, g.ny, rm, rp);
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int row = cy(i) > 0 ? rm : (cy(i) < 0 ? rp : re);
-      const int col = cx(i) > 0 ? colm : (cx(i) < 0 ? colp : colc);
-      const ST* plane = src + (long long)(s * 9 + i) * g.plane + (long long)row * g.pitch;
-      f[s][i] = (CT)plane[col];
+      const uint32_t ob = cx(i) > 0 ? ob_m : (cx(i) < 0 ? ob_p : ob_c);
+      const ST* base = src + (long long)(s * 9 + i) * g.plane + (long long)row * g.pitch;
+      f[s][i] = (CT)ld_at(base, ob);
     }
     if (WALLS) {
-      if (bottom) {
+      if (re == 0) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          f[s][wall_in_dir(0, j)] = (CT)wall_in[((0 * 2 + s) * 3 + j) * g.nx + colc];
+          f[s][wall_in_dir(0, j)] = (CT)wall_in[((0 * 2 + s) * 3 + j) * g.nx + col];
       }
-      if (top) {
+      if (re == g.ny - 1) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          f[s][wall_in_dir(1, j)] = (CT)wall_in[((1 * 2 + s) * 3 + j) * g.nx + colc];
+          f[s][wall_in_dir(1, j)] = (CT)wall_in[((1 * 2 + s) * 3 + j) * g.nx + col];
       }
     }
   }
 }
 
+// Density and pseudopotential of a pulled row (Sec. II; Eq. (5)).  With
+// deviation storage the LDS record holds deviations from the reference,
+// d_s = rho_s - rho_ref_s = sum_i delta_is and psi_s - psi(rho_ref_s), so
+// that stencil differences lose no digits to the common background.
 template <typename CT, bool DEV>
 __device__ __forceinline__ Fld<CT> make_fields(const Params<CT, DEV>& P, const CT (&f)[2][9]) {
   CT r[2];
@@ -140,71 +202,82 @@ __device__ __forceinline__ Fld<CT> make_fields(const Params<CT, DEV>& P, const C
     CT acc = f[s][0];
 #pragma unroll
     for (int i = 1; i < 9; ++i) acc += f[s][i];
-    r[s] = DEV ? P.rref[s] + acc : acc;
+    r[s] = acc;
   }
   Fld<CT> o;
   o.ra = r[0];
   o.rb = r[1];
-  o.pa = P.rho0 * (CT(1) - exp_ct(-r[0] * P.inv_rho0));
-  o.pb = P.rho0 * (CT(1) - exp_ct(-r[1] * P.inv_rho0));
+  if (DEV) {
+    o.pa = -P.pscale[0] * expm1_ct(-r[0] * P.inv_rho0);
+    o.pb = -P.pscale[1] * expm1_ct(-r[1] * P.inv_rho0);
+  } else {
+    o.pa = P.rho0 * (CT(1) - exp_ct(-r[0] * P.inv_rho0));
+    o.pb = P.rho0 * (CT(1) - exp_ct(-r[1] * P.inv_rho0));
+  }
   return o;
 }
 
+// The twelve +-c pairs of the 24 interaction neighbours: (cx, cy, class),
+// class 0..4 for |c|^2 = 1, 2, 4, 5, 8.  The first four are the first belt.
+__host__ __device__ constexpr int pair_cx(int m) {
+  return m == 0 ? 1 : m == 1 ? 0 : m == 2 ? 1 : m == 3 ? 1 : m == 4 ? 2 : m == 5 ? 0 :
+         m == 6 ? 2 : m == 7 ? 2 : m == 8 ? 1 : m == 9 ? 1 : m == 10 ? 2 : 2;
+}
+__host__ __device__ constexpr int pair_cy(int m) {
+  return m == 0 ? 0 : m == 1 ? 1 : m == 2 ? 1 : m == 3 ? -1 : m == 4 ? 0 : m == 5 ? 2 :
+         m == 6 ? 1 : m == 7 ? -1 : m == 8 ? 2 : m == 9 ? -2 : m == 10 ? 2 : -2;
+}
+__host__ __device__ constexpr int pair_class(int m) {
+  return m < 2 ? 0 : m < 4 ? 1 : m < 6 ? 2 : m < 10 ? 3 : 4;
+}
+
+// Collide the sites of lattice row y whose stencil rows sit in LDS ring
+// slots slot[0..4] (dy = -2..2).  Lane l owns LDS column l + 2.
 template <typename CT, bool DEV, bool WALLS, int MODE, typename ST>
 __device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, DEV>& P,
-                                            const Fld<CT>* __restrict__ ring, int lane,
-                                            const int (&slot)[5], int y, int colc,
+                                            const Fld<CT>* __restrict__ ring, int lc,
+                                            const int (&slot)[5], int y, int col, uint32_t ob_c,
                                             const CT (&f)[2][9], double (&acc)[kNRed],
                                             double (&wacc)[2], bool& bad) {
   const Geometry& g = a.g;
-  auto R = [&](int dy, int dx) -> const Fld<CT>& { return ring[slot[dy + 2] * kWave + lane + dx]; };
-  const Fld<CT> c0 = R(0, 0);
-  // first belt: full records
-  const Fld<CT> e = R(0, 1), w = R(0, -1), n = R(1, 0), s = R(-1, 0);
-  const Fld<CT> ne = R(1, 1), sw = R(-1, -1), nw = R(1, -1), se = R(-1, 1);
-  // second belt: psi only.  Index order: (2,0) (-2,0) (0,2) (0,-2)
-  // (2,1) (-2,-1) (2,-1) (-2,1) (1,2) (-1,-2) (1,-2) (-1,2) (2,2) (-2,-2) (2,-2) (-2,2)
-  const int b2dx[16] = {2, -2, 0, 0, 2, -2, 2, -2, 1, -1, 1, -1, 2, -2, 2, -2};
-  const int b2dy[16] = {0, 0, 2, -2, 1, -1, -1, 1, 2, -2, -2, 2, 2, -2, -2, 2};
-  CT qa[16], qb[16];
+  constexpr int W = kWave + 4;
+  auto at = [&](int dy, int dx) -> const Fld<CT>& { return ring[slot[dy + 2] * W + lc + dx]; };
+  // Shan-Chen sums over +-c pairs (Eq. (2)): S_s = sum_i k_s(i) psi_s(r + c_i) c_i,
+  // X_s = sum_{belt 1} (G_AB / rho0^2) w_i rho_other(r + c_i) c_i.
+  CT Sxa = 0, Sya = 0, Sxb = 0, Syb = 0, Xxa = 0, Xya = 0, Xxb = 0, Xyb = 0;
 #pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const Fld<CT>& v = R(b2dy[m], b2dx[m]);
-    qa[m] = v.pa;
-    qb[m] = v.pb;
+  for (int m = 0; m < 12; ++m) {
+    const int px = pair_cx(m), py = pair_cy(m), k = pair_class(m);
+    const Fld<CT>& hi = at(py, px);
+    const Fld<CT>& lo = at(-py, -px);
+    const CT da = hi.pa - lo.pa, db = hi.pb - lo.pb;
+    if (px) {
+      Sxa += (P.k[0][k] * (CT)px) * da;
+      Sxb += (P.k[1][k] * (CT)px) * db;
+    }
+    if (py) {
+      Sya += (P.k[0][k] * (CT)py) * da;
+      Syb += (P.k[1][k] * (CT)py) * db;
+    }
+    if (m < 4) {
+      const CT ea = hi.ra - lo.ra, eb = hi.rb - lo.rb;  // A's density acts on B and back
+      if (px) {
+        Xxa += (P.kx[k] * (CT)px) * eb;
+        Xxb += (P.kx[k] * (CT)px) * ea;
+      }
+      if (py) {
+        Xya += (P.kx[k] * (CT)py) * eb;
+        Xyb += (P.kx[k] * (CT)py) * ea;
+      }
+    }
   }
-  CT F[2][2];
-#pragma unroll
-  for (int sp = 0; sp < 2; ++sp) {
-    const CT* q = sp == 0 ? qa : qb;
-    auto P1 = [&](const Fld<CT>& v) { return sp == 0 ? v.pa : v.pb; };
-    auto Ro = [&](const Fld<CT>& v) { return sp == 0 ? v.rb : v.ra; };
-    // belt 1, |c|^2 = 1 and 2
-    const CT d1x = P1(e) - P1(w), d1y = P1(n) - P1(s);
-    const CT da = P1(ne) - P1(sw), db = P1(se) - P1(nw);
-    const CT d2x = da + db, d2y = da - db;
-    // belt 2
-    const CT d4x = CT(2) * (q[0] - q[1]), d4y = CT(2) * (q[2] - q[3]);
-    const CT a1 = q[4] - q[5], a2 = q[6] - q[7], a3 = q[8] - q[9], a4 = q[10] - q[11];
-    const CT d5x = CT(2) * (a1 + a2) + (a3 + a4), d5y = (a1 - a2) + CT(2) * (a3 - a4);
-    const CT c1 = q[12] - q[13], c2 = q[14] - q[15];
-    const CT d8x = CT(2) * (c1 + c2), d8y = CT(2) * (c1 - c2);
-    const CT Sx = P.k[sp][0] * d1x + P.k[sp][1] * d2x + P.k[sp][2] * d4x + P.k[sp][3] * d5x +
-                  P.k[sp][4] * d8x;
-    const CT Sy = P.k[sp][0] * d1y + P.k[sp][1] * d2y + P.k[sp][2] * d4y + P.k[sp][3] * d5y +
-                  P.k[sp][4] * d8y;
-    // cross term on the other species' density
-    const CT x1x = Ro(e) - Ro(w), x1y = Ro(n) - Ro(s);
-    const CT xa = Ro(ne) - Ro(sw), xb = Ro(se) - Ro(nw);
-    const CT Xx = P.kx[0] * x1x + P.kx[1] * (xa + xb);
-    const CT Xy = P.kx[0] * x1y + P.kx[1] * (xa - xb);
-    const CT psi0 = sp == 0 ? c0.pa : c0.pb;
-    const CT rho0s = sp == 0 ? c0.ra : c0.rb;
-    F[sp][0] = -psi0 * Sx - rho0s * Xx;
-    F[sp][1] = -psi0 * Sy - rho0s * Xy;
-  }
-  // moments and velocities (Eq. (1) and the common velocity below it)
-  const CT rho[2] = {c0.ra, c0.rb};
+  const Fld<CT> c0 = at(0, 0);
+  // centre values (deviation records add the references back)
+  const CT rho[2] = {DEV ? P.rref[0] + c0.ra : c0.ra, DEV ? P.rref[1] + c0.rb : c0.rb};
+  const CT psi[2] = {DEV ? P.pref[0] + c0.pa : c0.pa, DEV ? P.pref[1] + c0.pb : c0.pb};
+  const CT F[2][2] = {{-psi[0] * Sxa - rho[0] * Xxa, -psi[0] * Sya - rho[0] * Xya},
+                      {-psi[1] * Sxb - rho[1] * Xxb, -psi[1] * Syb - rho[1] * Xyb}};
+  // moments and the common velocity (Eq. (1) and the definition of u below it)
   CT jx[2], jy[2];
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp) {
@@ -212,13 +285,12 @@ __device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, 
     jy[sp] = (f[sp][2] - f[sp][4]) + (f[sp][5] - f[sp][8]) + (f[sp][6] - f[sp][7]);
     if (!(rho[sp] > CT(0)) || !(rho[sp] < CT(1e30))) bad = true;
   }
-  const CT inv_den = CT(1) / (rho[0] * P.om[0] + rho[1] * P.om[1]);
+  const CT inv_den = rcp_ct(rho[0] * P.om[0] + rho[1] * P.om[1]);
   const CT ux = (jx[0] * P.om[0] + jx[1] * P.om[1]) * inv_den;
   const CT uy = (jy[0] * P.om[0] + jy[1] * P.om[1]) * inv_den;
 
   if (MODE == kObserve) {
-    const int x = colc;
-    const long long site = (long long)y * g.nx + x;
+    const long long site = (long long)y * g.nx + col;
     const long long n = (long long)g.nx * g.ny;
     const double rt = (double)rho[0] + (double)rho[1];
     const double jtx = (double)jx[0] + (double)jx[1], jty = (double)jy[0] + (double)jy[1];
@@ -253,60 +325,70 @@ __device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, 
     return;
   }
 
-  // BGK relaxation towards the equilibrium at v_s = u' + tau_s F_s / rho_s
-  CT post[2][9];
+  ST* __restrict__ dst = (ST*)a.dst;
+  double mom = 0;
+  const bool wall_row = WALLS && (y == 0 || y == g.ny - 1);
+  const int wl = (WALLS && y == g.ny - 1) ? 1 : 0;
 #pragma unroll
   for (int sp = 0; sp < 2; ++sp) {
-    const CT ir = CT(1) / rho[sp];
+    // BGK relaxation towards the equilibrium at v_s = u' + tau_s F_s / rho_s
+    const CT ir = rcp_ct(rho[sp]);
     const CT vx = ux + P.tau[sp] * F[sp][0] * ir;
     const CT vy = uy + P.tau[sp] * F[sp][1] * ir;
     const CT usq = CT(1.5) * (vx * vx + vy * vy);
-    const CT drho = DEV ? rho[sp] - P.rref[sp] : CT(0);
+    const CT drho = DEV ? (sp == 0 ? c0.ra : c0.rb) : CT(0);  // sum of the deviations
+    CT post[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const CT cu = (CT)cx(i) * vx + (CT)cy(i) * vy;
       const CT poly = cu * (CT(3) + CT(4.5) * cu) - usq;
-      // f^eq_i = w_i rho (1 + poly); deviation form: f^eq_i - w_i rho_ref
+      // f^eq_i = w_i rho (1 + poly); deviation form: f^eq_i - w_i rho_ref = w_i (d + rho poly)
       const CT feq = DEV ? wq<CT>(i) * (drho + rho[sp] * poly) : wq<CT>(i) * rho[sp] * (CT(1) + poly);
-      post[sp][i] = f[sp][i] + P.om[sp] * (feq - f[sp][i]);
+      post[i] = f[sp][i] + P.om[sp] * (feq - f[sp][i]);
+      const ST* b = dst + (long long)(sp * 9 + i) * g.plane + (long long)y * g.pitch;
+      st_at(const_cast<ST*>(b), ob_c, (ST)post[i]);
     }
-  }
-  ST* dst = (ST*)a.dst;
-#pragma unroll
-  for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-    for (int i = 0; i < 9; ++i)
-      dst[(long long)(sp * 9 + i) * g.plane + (long long)y * g.pitch + colc] = (ST)post[sp][i];
-
-  if (WALLS) {
-    const bool bottom = y == 0, top = y == g.ny - 1;
-    if (bottom || top) {
-      const int wl = top ? 1 : 0;
-      const CT uwall = top ? P.uw : -P.uw;
+    if (WALLS && wall_row) {
+      const CT uwall = wl ? P.uw : -P.uw;
       ST* wall_out = (ST*)a.wall_out;
-      double mom = 0;
 #pragma unroll
-      for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-          // the j-th link leaves along o = wall_out_dir and comes back as wall_in_dir:
-          // f_back = f*_o - 2 w_o rho_w (c_o . u_w) / c_s^2, rho_w = rho_s(r, t)
-          const int o = bottom ? wall_out_dir(0, j) : wall_out_dir(1, j);
-          const CT corr = CT(6) * wq<CT>(o) * rho[sp] * ((CT)cx(o) * uwall);
-          const CT back = post[sp][o] - corr;
-          wall_out[((wl * 2 + sp) * 3 + j) * g.nx + colc] = (ST)back;
-          const double full = (double)post[sp][o] + (DEV ? wq<double>(o) * (double)P.rref[sp] : 0.0);
-          mom += (double)cx(o) * (2.0 * full - (double)corr);
-        }
-      wacc[wl] += mom;
+      for (int j = 0; j < 3; ++j) {
+        // the j-th link leaves along o and returns as wall_in_dir:
+        // f_back = f*_o - 2 w_o rho_w (c_o . u_w) / c_s^2, rho_w = rho_s(r, t).
+        // o is wall_out_dir(wl, j); both walls' o share the weight class.
+        const int o0 = wall_out_dir(0, j), o1 = wall_out_dir(1, j);
+        const CT po = wl ? post[o1] : post[o0];
+        const int cxo = wl ? cx(o1) : cx(o0);
+        const CT corr = CT(6) * wq<CT>(o0) * rho[sp] * ((CT)cxo * uwall);
+        wall_out[((wl * 2 + sp) * 3 + j) * g.nx + col] = (ST)(po - corr);
+        const double full = (double)po + (DEV ? wq<double>(o0) * (double)P.rref[sp] : 0.0);
+        mom += (double)cxo * (2.0 * full - (double)corr);
+      }
     }
   }
+  if (WALLS && wall_row) wacc[wl] += mom;
 }
 
+template <int N, typename Fn, int... I>
+__device__ __forceinline__ void static_for_impl(Fn&& fn, std::integer_sequence<int, I...>) {
+  (fn(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  static_for_impl<N>(fn, std::make_integer_sequence<int, N>{});
+}
 
-template <typename ST, typename CT, bool DEV, bool WALLS, int MODE>
+// One wavefront per (strip, segment) tile.  Lane l owns column x0 + l of a
+// 64-column strip (line-aligned); lanes 0..3 also pull the four ring columns
+// x0 - 2, x0 - 1, x0 + w, x0 + w + 1 (w = strip width).  Even segments
+// march up the rows, odd ones down, so two neighbouring segments reach
+// their shared ring rows at the same time and the second read hits L2.
+// PF = 1 issues the pull of the next row before the current collision.
+template <typename ST, typename CT, bool DEV, bool WALLS, int MODE, int PF>
 __global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
-  __shared__ Fld<CT> ring[kRing * kWave];
+  constexpr int W = kWave + 4;
+  constexpr int NSET = 3 + PF;
+  __shared__ Fld<CT> ring[kRing * W];
   const Geometry& g = a.g;
   const int b = blockIdx.x;
   const int tile = (b & 7) * g.tiles_per_xcd + (b >> 3);
@@ -315,56 +397,77 @@ __global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
   const int seg = tile / g.nstrips;
   const int lane = threadIdx.x;
   const int nx = g.nx, ny = g.ny;
-  const int x0 = (int)((long long)strip * nx / g.nstrips);
-  const int x1 = (int)((long long)(strip + 1) * nx / g.nstrips);
+  const int x0 = strip * kWave;
+  const int width = min(kWave, nx - x0);
   const int y0 = (int)((long long)seg * ny / g.nsegs);
   const int y1 = (int)((long long)(seg + 1) * ny / g.nsegs);
-  const int nint = x1 - x0;
-  const bool active = lane >= 2 && lane < 2 + nint;
-  const int colc = wrap(x0 - 2 + lane, nx);
-  const int colm = wrap(x0 - 3 + lane, nx);  // source column of c_x = +1
-  const int colp = wrap(x0 - 1 + lane, nx);  // source column of c_x = -1
+  const int dir = (seg & 1) ? -1 : 1;
+  const bool active = lane < width;
+  // interior column (inactive lanes read a valid duplicate column)
+  const int col = active ? x0 + lane : wrap(x0 + lane, nx);
+  const uint32_t esz = sizeof(ST);
+  const uint32_t ob_c = (uint32_t)col * esz;
+  const uint32_t ob_m = (uint32_t)(col == 0 ? nx - 1 : col - 1) * esz;
+  const uint32_t ob_p = (uint32_t)(col == nx - 1 ? 0 : col + 1) * esz;
+  // ring column of lanes 0..3 and its LDS position
+  const int rl = lane & 3;
+  const int rcol = wrap(rl < 2 ? x0 - 2 + rl : x0 + width + (rl - 2), nx);
+  const int rpos = rl < 2 ? rl : width + rl;
+  const uint32_t rb_c = (uint32_t)rcol * esz;
+  const uint32_t rb_m = (uint32_t)(rcol == 0 ? nx - 1 : rcol - 1) * esz;
+  const uint32_t rb_p = (uint32_t)(rcol == nx - 1 ? 0 : rcol + 1) * esz;
+
   const Params<CT, DEV> P(a.c);
   const ST* __restrict__ src = (const ST*)a.src;
   const ST* __restrict__ wall_in = (const ST*)a.wall_in;
 
-  CT fr[3][2][9];
+  CT fr[NSET][2][9];
+  CT rg[2][9];
   double acc[kNRed];
 #pragma unroll
   for (int m = 0; m < kNRed; ++m) acc[m] = 0.0;
   double wacc[2] = {0.0, 0.0};
   bool bad = false;
-  const int K = (y1 - y0) + 4;  // rows y0-2 .. y1+1
+  const int K = (y1 - y0) + 4;  // field rows pulled: the segment plus two ring rows each side
+  const int rstart = dir > 0 ? y0 - 2 : y1 + 1;
 
-  auto iter = [&](int k, auto cur_tag, auto old_tag) {
-    constexpr int cur = decltype(cur_tag)::value;
-    constexpr int old = decltype(old_tag)::value;
-    const int r = y0 - 2 + k;
-    int re;
-    if (WALLS) {
-      re = r < 0 ? -1 - r : (r >= ny ? 2 * ny - 1 - r : r);  // mirror ghost rows
-    } else {
-      re = r < 0 ? r + ny : (r >= ny ? r - ny : r);
-      re = wrap(re, ny);  // lattices shorter than the ring
-    }
-    pull_row<ST, CT, WALLS>(a, src, wall_in, re, colm, colc, colp, fr[cur]);
-    const Fld<CT> fl = make_fields<CT, DEV>(P, fr[cur]);
-    lds_fence();
-    ring[(k % kRing) * kWave + lane] = fl;
-    lds_fence();
-    if (k >= 4 && active) {
-      int slot[5];
-#pragma unroll
-      for (int d = 0; d < 5; ++d) slot[d] = (k - 4 + d) % kRing;
-      collide_row<CT, DEV, WALLS, MODE, ST>(a, P, ring, lane, slot, r - 2, colc, fr[old], acc,
-                                            wacc, bad);
-    }
+  auto lattice_row = [&](int k) {
+    const int r = rstart + dir * k;
+    if (WALLS) return r < 0 ? -1 - r : (r >= ny ? 2 * ny - 1 - r : r);  // mirrored ghost rows
+    return r < 0 ? r + ny : (r >= ny ? r - ny : r);
+  };
+  auto pull_row = [&](int k, CT (&dstf)[2][9]) {
+    const int re = lattice_row(k);
+    pull<ST, CT, WALLS>(g, src, wall_in, re, ob_m, ob_c, ob_p, col, dstf);
+    if (lane < 4) pull<ST, CT, WALLS>(g, src, wall_in, re, rb_m, rb_c, rb_p, rcol, rg);
   };
 
-  for (int k0 = 0; k0 < K; k0 += 3) {
-    iter(k0, std::integral_constant<int, 0>{}, std::integral_constant<int, 1>{});
-    if (k0 + 1 < K) iter(k0 + 1, std::integral_constant<int, 1>{}, std::integral_constant<int, 2>{});
-    if (k0 + 2 < K) iter(k0 + 2, std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{});
+  if (PF) pull_row(0, fr[0]);
+  for (int k0 = 0; k0 < K; k0 += NSET) {
+    static_for<NSET>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      const int k = k0 + j;
+      if (k >= K) return;
+      if (!PF) pull_row(k, fr[j]);
+      // fields of the pulled row into LDS slot k % 5
+      const Fld<CT> fl = make_fields<CT, DEV>(P, fr[j]);
+      Fld<CT> flr;
+      if (lane < 4) flr = make_fields<CT, DEV>(P, rg);
+      lds_fence();
+      Fld<CT>* row = ring + (k % kRing) * W;
+      if (active) row[lane + 2] = fl;
+      if (lane < 4) row[rpos] = flr;
+      lds_fence();
+      if (PF && k + 1 < K) pull_row(k + 1, fr[(j + 1) % NSET]);
+      if (k >= 4 && active) {
+        int slot[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) slot[d] = (k - 2 + dir * (d - 2)) % kRing;
+        const int y = lattice_row(k - 2);
+        collide_row<CT, DEV, WALLS, MODE, ST>(a, P, ring, lane + 2, slot, y, col, ob_c,
+                                              fr[(j + NSET - 2) % NSET], acc, wacc, bad);
+      }
+    });
   }
 
   if (__any(bad) && lane == 0) atomicOr(a.flag, 1);
@@ -475,25 +578,25 @@ __global__ __launch_bounds__(256) void k_noise(int nx, int ny, uint64_t seed, do
   rho[q] = (s == 0 ? ma : mb) + amp * (2.0 * u01 - 1.0);
 }
 
-template <int MODE>
+template <int MODE, int PF>
 hipError_t launch_march(const StepArgs& a, bool fp64, bool walls, hipStream_t st) {
   const dim3 grid(8 * a.g.tiles_per_xcd), block(kWave);
   if (fp64) {
     if (walls)
-      hipLaunchKernelGGL((k_march<double, double, false, true, MODE>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<double, double, false, true, MODE, PF>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_march<double, double, false, false, MODE>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<double, double, false, false, MODE, PF>), grid, block, 0, st, a);
   } else if (MODE == kStep) {
     if (walls)
-      hipLaunchKernelGGL((k_march<float, float, true, true, MODE>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<float, float, true, true, MODE, PF>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_march<float, float, true, false, MODE>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<float, float, true, false, MODE, PF>), grid, block, 0, st, a);
   } else {
     // observation of FP32 deviation storage is evaluated in FP64
     if (walls)
-      hipLaunchKernelGGL((k_march<float, double, true, true, MODE>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<float, double, true, true, MODE, PF>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_march<float, double, true, false, MODE>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<float, double, true, false, MODE, PF>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -524,12 +627,13 @@ hipError_t launch_init_any(const Geometry& g, const Coefs& c, bool fp64, bool wa
 
 }  // namespace
 
-hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, hipStream_t st) {
-  return launch_march<kStep>(a, fp64, walls, st);
+hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, int prefetch, hipStream_t st) {
+  return prefetch ? launch_march<kStep, 1>(a, fp64, walls, st)
+                  : launch_march<kStep, 0>(a, fp64, walls, st);
 }
 
 hipError_t launch_observe(const StepArgs& a, bool fp64, bool walls, hipStream_t st) {
-  return launch_march<kObserve>(a, fp64, walls, st);
+  return launch_march<kObserve, 0>(a, fp64, walls, st);
 }
 
 hipError_t launch_reduce_tiles(const double* in, int ntiles, int width, double* out,

@@ -29,6 +29,7 @@ struct lb_lattice {
   double* red_out = nullptr;
   int* flag = nullptr;
   int64_t step = 0, avg_start = 0;
+  int prefetch = 1;
   bool initialized = false;
   std::string err;
 };
@@ -75,11 +76,12 @@ lbk::Geometry make_geometry(const lb_params* p) {
   lbk::Geometry g{};
   g.nx = p->nx;
   g.ny = p->ny;
-  g.pitch = (p->nx + 31) / 32 * 32;
+  g.pitch = (p->nx + lbk::kWave - 1) / lbk::kWave * lbk::kWave;  // strips start on a line
   g.plane = (long long)g.pitch * g.ny;
-  g.nstrips = (p->nx + lbk::kStrip - 1) / lbk::kStrip;
-  // Aim for >= 4096 wavefronts (16 per CU) with segments of 8..64 rows.
-  int nsegs = (4096 + g.nstrips - 1) / g.nstrips;
+  g.nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
+  // Aim for about 2048 wavefronts (8 per CU) with segments of 8..64 rows:
+  // fewer, taller segments re-read fewer ring rows, more keep HBM busy.
+  int nsegs = (2048 + g.nstrips - 1) / g.nstrips;
   nsegs = std::min(nsegs, std::max(1, p->ny / 8));
   nsegs = std::max(nsegs, (p->ny + 63) / 64);
   if (const char* e = std::getenv("LBSOFT_SEG_H")) {
@@ -115,6 +117,30 @@ Layout make_layout(const lb_params* p, const lbk::Geometry& g) {
   return L;
 }
 
+// Derived reference values and FP32 copies of the constants for the FP32
+// kernels.  rho_ref is first rounded to FP32 so both precisions of the
+// kernels see the same reference.
+void round_coefs(lbk::Coefs& c) {
+  for (int s = 0; s < 2; ++s) {
+    c.rho_ref[s] = (double)(float)c.rho_ref[s];
+    c.psi_ref[s] = c.rho0 * -std::expm1(-c.rho_ref[s] / c.rho0);
+    c.psi_scale[s] = c.rho0 * std::exp(-c.rho_ref[s] / c.rho0);
+    c.f_psi_ref[s] = (float)c.psi_ref[s];
+    c.f_psi_scale[s] = (float)c.psi_scale[s];
+  }
+  for (int s = 0; s < 2; ++s) {
+    for (int m = 0; m < 5; ++m) c.f_kself[s][m] = (float)c.kself[s][m];
+    c.f_tau[s] = (float)c.tau[s];
+    c.f_omega[s] = (float)c.omega[s];
+    c.f_rho_ref[s] = (float)c.rho_ref[s];
+  }
+  c.f_kcross[0] = (float)c.kcross[0];
+  c.f_kcross[1] = (float)c.kcross[1];
+  c.f_rho0 = (float)c.rho0;
+  c.f_inv_rho0 = (float)c.inv_rho0;
+  c.f_u_wall = (float)c.u_wall;
+}
+
 lbk::Coefs make_coefs(const lb_params* p) {
   lbk::Coefs c{};
   for (int s = 0; s < 2; ++s) {
@@ -133,6 +159,7 @@ lbk::Coefs make_coefs(const lb_params* p) {
   c.rho0 = p->rho0;
   c.inv_rho0 = 1.0 / p->rho0;
   c.u_wall = p->u_wall;
+  round_coefs(c);
   return c;
 }
 
@@ -212,6 +239,7 @@ int set_rho_ref_from(lb_lattice* L, const double* ra, const double* rb, size_t n
     for (size_t k = 0; k < n; ++k) acc += r[s][k];
     L->c.rho_ref[s] = acc / (double)n;
   }
+  round_coefs(L->c);
   return LB_OK;
 }
 
@@ -267,6 +295,8 @@ int lb_create(const lb_params* p, void* hip_stream, lb_lattice** out) {
   L->walls = p->boundary == LB_COUETTE_Y;
   L->elem = L->fp64 ? 8 : 4;
   L->stream = (hipStream_t)hip_stream;
+  L->prefetch = L->fp64 ? 0 : 1;
+  if (const char* e = std::getenv("LBSOFT_PREFETCH")) L->prefetch = std::atoi(e) ? 1 : 0;
   if (hipGetDevice(&L->device) != hipSuccess) {
     delete L;
     return LB_E_DEVICE;
@@ -364,6 +394,7 @@ int lb_init_noise(lb_lattice* L, uint64_t seed, double mean_a, double mean_b, do
   if (!L->fp64) {
     L->c.rho_ref[0] = L->p.rho_ref[0] > 0 ? L->p.rho_ref[0] : mean_a;
     L->c.rho_ref[1] = L->p.rho_ref[1] > 0 ? L->p.rho_ref[1] : mean_b;
+    round_coefs(L->c);
   }
   const size_t n = (size_t)L->g.nx * L->g.ny;
   DevTmp t;
@@ -380,7 +411,7 @@ int lb_step(lb_lattice* L, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     lbk::StepArgs a = base_args(L, (int)(L->step & 1));
     a.accumulate_wall = L->walls ? 1 : 0;
-    HIPCK(L, lbk::launch_step(a, L->fp64, L->walls, L->stream));
+    HIPCK(L, lbk::launch_step(a, L->fp64, L->walls, L->prefetch, L->stream));
     ++L->step;
   }
   return LB_OK;
