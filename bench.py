@@ -104,10 +104,46 @@ def traffic_for(precision, sites):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
-    ent = rec.get(precision)
-    if not ent or rec.get("kernel_sha256_16") != kernel_hash() or ent.get("sites") != sites:
+    ent = rec.get(f"{precision}@{sites}")
+    if not ent or rec.get("kernel_sha256_16") != kernel_hash():
         return None
     return ent["bytes_per_launch"]
+
+
+def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv,
+                    copy_bytes=1 << 30):
+    """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs into HBM
+    bytes per step launch.  Each counter is scaled by what it reads for a
+    plain copy of copy_bytes (the --copy-probe run), and the result is stored
+    with the hash of the kernel source it was measured on."""
+    import csv
+    import statistics
+
+    def per_dispatch(path, pred):
+        vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if pred(r["Kernel_Name"])]
+        if not vals:
+            raise SystemExit(f"no matching dispatches in {path}")
+        return statistics.median(vals)
+
+    step = lambda n: n.startswith("void lbk::") and "k_march<" in n and ", 0, " in n
+    copy = lambda n: "copyBuffer" in n
+    kib = copy_bytes / 1024
+    f_scale = kib / per_dispatch(copy_fetch_csv, copy)
+    w_scale = kib / per_dispatch(copy_write_csv, copy)
+    fetch = per_dispatch(fetch_csv, step) * f_scale * 1024
+    write = per_dispatch(write_csv, step) * w_scale * 1024
+    rec = {}
+    if os.path.exists(TRAFFIC_FILE):
+        rec = json.load(open(TRAFFIC_FILE))
+    if rec.get("kernel_sha256_16") != kernel_hash():
+        rec = {"kernel_sha256_16": kernel_hash()}
+    rec[f"{precision}@{sites}"] = {"sites": sites, "bytes_per_launch": fetch + write, "fetch_bytes": fetch,
+                      "write_bytes": write, "fetch_scale": f_scale, "write_scale": w_scale,
+                      "algorithmic_bytes": BYTES_PER_SITE[precision] * sites}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec[f"{precision}@{sites}"]))
 
 
 def copy_probe(mib: int = 1024, reps: int = 5):
@@ -134,7 +170,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the 4096x1024 HBM-resident probe")
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 1 GiB copy")
+    ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="store HBM traffic per step from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(args.precision, args.nx * args.ny, *args.ingest_counters)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -178,11 +219,14 @@ def main():
         print(f"# probe 4096x1024: {pr['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
     sites = nx * ny
+    pop_bytes = BYTES_PER_SITE[args.precision] * sites  # both population buffers (half each)
     roof = {"bound": "hbm", "achieved": main_run["achieved_gbs"], "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": main_run["achieved_gbs"] / PEAK_HBM_GBS,
             "traffic": traffic_for(args.precision, sites),
             "kernel": "k_march (step)", "bytes_per_site": BYTES_PER_SITE[args.precision],
-            "units_per_launch": sites}
+            "units_per_launch": sites,
+            # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed
+            "cache_resident": pop_bytes <= (256 << 20)}
     line = {
         "metric": "two-species MLUPS",
         "value": main_run["mlups"],

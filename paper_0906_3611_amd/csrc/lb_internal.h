@@ -17,6 +17,15 @@ constexpr int kRing = 5;
 
 enum Mode : int { kStep = 0, kObserve = 1 };
 
+// Population layout: lattice row y is (pitch / 64) blocks of 64 sites; a
+// block holds the 18 populations (species-major, D2Q9 order) of its sites,
+// each as 64 consecutive values.  Element (s, i, y, x) is at
+//   y * row_elems + (x / 64) * 18 * 64 + (s * 9 + i) * 64 + x % 64,
+// so a wavefront touches one contiguous block per lattice row.
+__host__ __device__ inline long long pop_index(long long row_elems, int s, int i, int y, int x) {
+  return (long long)y * row_elems + (long long)(x >> 6) * (18 * 64) + (s * 9 + i) * 64 + (x & 63);
+}
+
 // Number of FP64 values each wave writes in observe mode.
 constexpr int kNRed = 8;  // massA, massB, momx, momy, momphys_x, momphys_y, pxy, spare
 
@@ -41,7 +50,7 @@ struct Coefs {
 
 struct Geometry {
   int nx, ny, pitch;
-  long long plane;  // elements in one (species, direction) plane = pitch * ny
+  long long row_elems;  // elements of one lattice row: (pitch / 64) blocks x 18 x 64
   int nstrips, seg_h, nsegs, ntiles, tiles_per_xcd;
 };
 
@@ -60,9 +69,15 @@ struct StepArgs {
   Coefs c;
 };
 
+// Code variants of the step kernel (tuning choices, same arithmetic).
+struct StepVariant {
+  int prefetch;       // issue the next row's pull before the current collision
+  int stream_stores;  // nontemporal population stores
+};
+
 // Launchers (lb_kernels.hip).  All return hipError_t of the launch.
-// prefetch: issue the next row's pull before the current collision.
-hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, int prefetch, hipStream_t st);
+hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, const StepVariant& v,
+                       hipStream_t st);
 hipError_t launch_observe(const StepArgs& a, bool fp64, bool walls, hipStream_t st);
 // Fixed-order sum of ntiles * width per-tile values into out[width].
 hipError_t launch_reduce_tiles(const double* in, int ntiles, int width, double* out,

@@ -1,9 +1,12 @@
 // HIP kernels for gfx950 of the two-species Shan-Chen lattice Boltzmann step
 // (Benzi et al., arXiv:0906.3611, Sec. II).
 //
-// Layout.  Populations are structure-of-arrays planes [s][i][y][pitch] in
-// "pull" form: the buffer for time t holds, at site q and direction i, the
-// post-collision value that site q + c_i pulls when it streams into time t.
+// Layout.  Populations are stored in "pull" form: the buffer for time t
+// holds, at site q and direction i, the post-collision value that site
+// q + c_i pulls when it streams into time t.  Each lattice row is a run of
+// 64-site blocks, each block holding its 18 populations as 18 runs of 64
+// values (pop_index in lb_internal.h), so a wavefront reads and writes one
+// contiguous block per row instead of 18 separate planes.
 // A step reads one buffer and writes the other (ping-pong).  Under moving
 // walls the three links of a wall-adjacent site that come back from the
 // wall are kept in a small side buffer [wall][s][link][nx], written by the
@@ -140,9 +143,17 @@ template <typename T>
 __device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
   return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)byte_off);
 }
-template <typename T>
+// Population stores.  NT (streaming) stores keep the written buffer out of
+// the caches: right for lattices larger than the 256 MB Infinity Cache, whose
+// next-step reads come from HBM anyway, wrong for smaller ones, whose reads
+// the Infinity Cache would serve.
+template <bool NT, typename T>
 __device__ __forceinline__ void st_at(T* base, uint32_t byte_off, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)byte_off) = v;
+  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)byte_off);
+  if (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
 }
 
 // Source rows of a pull into lattice row re: rm for c_y = +1, rp for c_y = -1.
@@ -158,7 +169,8 @@ __device__ __forceinline__ void source_rows(int re, int ny, int& rm, int& rp) {
 }
 
 // Pull the 18 populations streaming into row re at column col.  ob_m / ob_c
-// / ob_p are the byte offsets of the source columns col - 1, col, col + 1
+// / ob_p are the in-row byte offsets (block and lane, population 0) of the
+// source columns col - 1, col, col + 1
 // (sources of c_x = +1, 0, -1).
 template <typename ST, typename CT, bool WALLS>
 __device__ __forceinline__ void pull(const Geometry& g, const ST* __restrict__ src,
@@ -172,7 +184,7 @@ __device__ __forceinline__ void pull(const Geometry& g, const ST* __restrict__ s
     for (int i = 0; i < 9; ++i) {
       const int row = cy(i) > 0 ? rm : (cy(i) < 0 ? rp : re);
       const uint32_t ob = cx(i) > 0 ? ob_m : (cx(i) < 0 ? ob_p : ob_c);
-      const ST* base = src + (long long)(s * 9 + i) * g.plane + (long long)row * g.pitch;
+      const ST* base = src + (long long)row * g.row_elems + (s * 9 + i) * kWave;
       f[s][i] = (CT)ld_at(base, ob);
     }
     if (WALLS) {
@@ -233,7 +245,10 @@ __host__ __device__ constexpr int pair_class(int m) {
 
 // Collide the sites of lattice row y whose stencil rows sit in LDS ring
 // slots slot[0..4] (dy = -2..2).  Lane l owns LDS column l + 2.
-template <typename CT, bool DEV, bool WALLS, int MODE, typename ST>
+#ifndef LDS_GROUP
+#define LDS_GROUP 0
+#endif
+template <typename CT, bool DEV, bool WALLS, int MODE, typename ST, bool NT>
 __device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, DEV>& P,
                                             const Fld<CT>* __restrict__ ring, int lc,
                                             const int (&slot)[5], int y, int col, uint32_t ob_c,
@@ -247,6 +262,8 @@ __device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, 
   CT Sxa = 0, Sya = 0, Sxb = 0, Syb = 0, Xxa = 0, Xya = 0, Xxb = 0, Xyb = 0;
 #pragma unroll
   for (int m = 0; m < 12; ++m) {
+    // keep the LDS reads of a few pairs in flight at a time, not all 25
+    if (LDS_GROUP > 0 && m % LDS_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
     const int px = pair_cx(m), py = pair_cy(m), k = pair_class(m);
     const Fld<CT>& hi = at(py, px);
     const Fld<CT>& lo = at(-py, -px);
@@ -345,8 +362,8 @@ __device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, 
       // f^eq_i = w_i rho (1 + poly); deviation form: f^eq_i - w_i rho_ref = w_i (d + rho poly)
       const CT feq = DEV ? wq<CT>(i) * (drho + rho[sp] * poly) : wq<CT>(i) * rho[sp] * (CT(1) + poly);
       post[i] = f[sp][i] + P.om[sp] * (feq - f[sp][i]);
-      const ST* b = dst + (long long)(sp * 9 + i) * g.plane + (long long)y * g.pitch;
-      st_at(const_cast<ST*>(b), ob_c, (ST)post[i]);
+      const ST* b = dst + (long long)y * g.row_elems + (sp * 9 + i) * kWave;
+      st_at<NT>(const_cast<ST*>(b), ob_c, (ST)post[i]);
     }
     if (WALLS && wall_row) {
       const CT uwall = wl ? P.uw : -P.uw;
@@ -384,7 +401,7 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // march up the rows, odd ones down, so two neighbouring segments reach
 // their shared ring rows at the same time and the second read hits L2.
 // PF = 1 issues the pull of the next row before the current collision.
-template <typename ST, typename CT, bool DEV, bool WALLS, int MODE, int PF>
+template <typename ST, typename CT, bool DEV, bool WALLS, int MODE, int PF, bool NT>
 __global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
   constexpr int W = kWave + 4;
   constexpr int NSET = 3 + PF;
@@ -406,16 +423,17 @@ __global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
   // interior column (inactive lanes read a valid duplicate column)
   const int col = active ? x0 + lane : wrap(x0 + lane, nx);
   const uint32_t esz = sizeof(ST);
-  const uint32_t ob_c = (uint32_t)col * esz;
-  const uint32_t ob_m = (uint32_t)(col == 0 ? nx - 1 : col - 1) * esz;
-  const uint32_t ob_p = (uint32_t)(col == nx - 1 ? 0 : col + 1) * esz;
+  auto in_row = [&](int c) { return (uint32_t)((c >> 6) * (18 * kWave) + (c & 63)) * esz; };
+  const uint32_t ob_c = in_row(col);
+  const uint32_t ob_m = in_row(col == 0 ? nx - 1 : col - 1);
+  const uint32_t ob_p = in_row(col == nx - 1 ? 0 : col + 1);
   // ring column of lanes 0..3 and its LDS position
   const int rl = lane & 3;
   const int rcol = wrap(rl < 2 ? x0 - 2 + rl : x0 + width + (rl - 2), nx);
   const int rpos = rl < 2 ? rl : width + rl;
-  const uint32_t rb_c = (uint32_t)rcol * esz;
-  const uint32_t rb_m = (uint32_t)(rcol == 0 ? nx - 1 : rcol - 1) * esz;
-  const uint32_t rb_p = (uint32_t)(rcol == nx - 1 ? 0 : rcol + 1) * esz;
+  const uint32_t rb_c = in_row(rcol);
+  const uint32_t rb_m = in_row(rcol == 0 ? nx - 1 : rcol - 1);
+  const uint32_t rb_p = in_row(rcol == nx - 1 ? 0 : rcol + 1);
 
   const Params<CT, DEV> P(a.c);
   const ST* __restrict__ src = (const ST*)a.src;
@@ -464,7 +482,7 @@ __global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
 #pragma unroll
         for (int d = 0; d < 5; ++d) slot[d] = (k - 2 + dir * (d - 2)) % kRing;
         const int y = lattice_row(k - 2);
-        collide_row<CT, DEV, WALLS, MODE, ST>(a, P, ring, lane + 2, slot, y, col, ob_c,
+        collide_row<CT, DEV, WALLS, MODE, ST, NT>(a, P, ring, lane + 2, slot, y, col, ob_c,
                                               fr[(j + NSET - 2) % NSET], acc, wacc, bad);
       }
     });
@@ -549,7 +567,7 @@ __global__ __launch_bounds__(256) void k_init(Geometry g, Coefs c, const double*
       } else {
         ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
       }
-      buf[(long long)(s * 9 + i) * g.plane + (long long)y * g.pitch + x] = (ST)value(s, i, xs, ys);
+      buf[pop_index(g.row_elems, s, i, y, x)] = (ST)value(s, i, xs, ys);
     }
   if (WALLS && (y == 0 || y == g.ny - 1)) {
     const int wl = y == 0 ? 0 : 1;
@@ -578,25 +596,25 @@ __global__ __launch_bounds__(256) void k_noise(int nx, int ny, uint64_t seed, do
   rho[q] = (s == 0 ? ma : mb) + amp * (2.0 * u01 - 1.0);
 }
 
-template <int MODE, int PF>
+template <int MODE, int PF, bool NT>
 hipError_t launch_march(const StepArgs& a, bool fp64, bool walls, hipStream_t st) {
   const dim3 grid(8 * a.g.tiles_per_xcd), block(kWave);
   if (fp64) {
     if (walls)
-      hipLaunchKernelGGL((k_march<double, double, false, true, MODE, PF>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<double, double, false, true, MODE, PF, NT>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_march<double, double, false, false, MODE, PF>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<double, double, false, false, MODE, PF, NT>), grid, block, 0, st, a);
   } else if (MODE == kStep) {
     if (walls)
-      hipLaunchKernelGGL((k_march<float, float, true, true, MODE, PF>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<float, float, true, true, MODE, PF, NT>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_march<float, float, true, false, MODE, PF>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<float, float, true, false, MODE, PF, NT>), grid, block, 0, st, a);
   } else {
     // observation of FP32 deviation storage is evaluated in FP64
     if (walls)
-      hipLaunchKernelGGL((k_march<float, double, true, true, MODE, PF>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<float, double, true, true, MODE, PF, NT>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((k_march<float, double, true, false, MODE, PF>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((k_march<float, double, true, false, MODE, PF, NT>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -627,13 +645,17 @@ hipError_t launch_init_any(const Geometry& g, const Coefs& c, bool fp64, bool wa
 
 }  // namespace
 
-hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, int prefetch, hipStream_t st) {
-  return prefetch ? launch_march<kStep, 1>(a, fp64, walls, st)
-                  : launch_march<kStep, 0>(a, fp64, walls, st);
+hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, const StepVariant& v,
+                       hipStream_t st) {
+  if (v.prefetch)
+    return v.stream_stores ? launch_march<kStep, 1, true>(a, fp64, walls, st)
+                           : launch_march<kStep, 1, false>(a, fp64, walls, st);
+  return v.stream_stores ? launch_march<kStep, 0, true>(a, fp64, walls, st)
+                         : launch_march<kStep, 0, false>(a, fp64, walls, st);
 }
 
 hipError_t launch_observe(const StepArgs& a, bool fp64, bool walls, hipStream_t st) {
-  return launch_march<kObserve, 0>(a, fp64, walls, st);
+  return launch_march<kObserve, 0, false>(a, fp64, walls, st);
 }
 
 hipError_t launch_reduce_tiles(const double* in, int ntiles, int width, double* out,

@@ -29,7 +29,7 @@ struct lb_lattice {
   double* red_out = nullptr;
   int* flag = nullptr;
   int64_t step = 0, avg_start = 0;
-  int prefetch = 1;
+  lbk::StepVariant variant{1, 0};
   bool initialized = false;
   std::string err;
 };
@@ -77,7 +77,7 @@ lbk::Geometry make_geometry(const lb_params* p) {
   g.nx = p->nx;
   g.ny = p->ny;
   g.pitch = (p->nx + lbk::kWave - 1) / lbk::kWave * lbk::kWave;  // strips start on a line
-  g.plane = (long long)g.pitch * g.ny;
+  g.row_elems = (long long)(g.pitch / lbk::kWave) * 18 * lbk::kWave;
   g.nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
   // Aim for about 2048 wavefronts (8 per CU) with segments of 8..64 rows:
   // fewer, taller segments re-read fewer ring rows, more keep HBM busy.
@@ -99,7 +99,7 @@ lbk::Geometry make_geometry(const lb_params* p) {
 Layout make_layout(const lb_params* p, const lbk::Geometry& g) {
   const size_t elem = p->precision == LB_FP64 ? 8 : 4;
   Layout L{};
-  L.pop_bytes = align_up(18ull * (size_t)g.plane * elem);
+  L.pop_bytes = align_up((size_t)g.row_elems * (size_t)g.ny * elem);
   size_t off = 0;
   L.buf = off;
   off += 2 * L.pop_bytes;
@@ -295,8 +295,10 @@ int lb_create(const lb_params* p, void* hip_stream, lb_lattice** out) {
   L->walls = p->boundary == LB_COUETTE_Y;
   L->elem = L->fp64 ? 8 : 4;
   L->stream = (hipStream_t)hip_stream;
-  L->prefetch = L->fp64 ? 0 : 1;
-  if (const char* e = std::getenv("LBSOFT_PREFETCH")) L->prefetch = std::atoi(e) ? 1 : 0;
+  // Defaults: prefetch for FP32 (registers allow it), streaming stores when
+  // the two population buffers exceed the 256 MB Infinity Cache.
+  L->variant.prefetch = L->fp64 ? 0 : 1;
+  L->variant.stream_stores = 0;
   if (hipGetDevice(&L->device) != hipSuccess) {
     delete L;
     return LB_E_DEVICE;
@@ -304,6 +306,9 @@ int lb_create(const lb_params* p, void* hip_stream, lb_lattice** out) {
   const Layout lay = make_layout(p, L->g);
   L->bytes = lay.total;
   L->pop_bytes = lay.pop_bytes;
+  L->variant.stream_stores = 2 * lay.pop_bytes > (256ull << 20) ? 1 : 0;
+  if (const char* e = std::getenv("LBSOFT_PREFETCH")) L->variant.prefetch = std::atoi(e) ? 1 : 0;
+  if (const char* e = std::getenv("LBSOFT_STREAM_STORES")) L->variant.stream_stores = std::atoi(e) ? 1 : 0;
   if (p->device_buffer) {
     if (p->device_bytes < lay.total || ((uintptr_t)p->device_buffer % kAlign) != 0) {
       delete L;
@@ -411,7 +416,7 @@ int lb_step(lb_lattice* L, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     lbk::StepArgs a = base_args(L, (int)(L->step & 1));
     a.accumulate_wall = L->walls ? 1 : 0;
-    HIPCK(L, lbk::launch_step(a, L->fp64, L->walls, L->prefetch, L->stream));
+    HIPCK(L, lbk::launch_step(a, L->fp64, L->walls, L->variant, L->stream));
     ++L->step;
   }
   return LB_OK;
