@@ -149,20 +149,69 @@ int lb_sync(lb_lattice* lat);
 /* Current time step t (host counter; no synchronization). */
 int64_t lb_current_step(const lb_lattice* lat);
 
-/* How a step is launched: the lattice is cut into nstrips column strips of
- * at most 64 columns and nsegs row segments; each (strip, segment) tile is
- * one 64-lane wavefront (one workgroup), grid_blocks workgroups per step. */
+/* How a step is launched: each lattice is cut into nstrips column strips of
+ * 64 columns (the last may be narrower) and nsegs row segments of about
+ * seg_h rows; each (strip, segment) tile is one 64-lane wavefront (one
+ * workgroup), grid_blocks workgroups per step.  prefetch / stream_stores /
+ * use_graph report the code variant in use (1 = on). */
 typedef struct {
   int32_t nstrips, nsegs, ntiles, grid_blocks, block_threads, pitch;
   size_t workspace_bytes;
-  size_t population_bytes;   /* one population buffer: 18 planes */
+  size_t population_bytes;   /* one population buffer of every lattice, summed */
+  int32_t seg_h, prefetch, stream_stores, use_graph;
 } lb_launch_info;
 int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
+
+/* Tuning knobs that leave the arithmetic unchanged (results stay bit for bit
+ * the same apart from the tile-order of observable reductions when seg_h
+ * changes).  Any argument < 0 keeps the current choice.
+ *   seg_h: row-segment height (0 = default policy); resets the wall averages.
+ *   prefetch: issue the next row's loads before the current collision.
+ *   stream_stores: nontemporal population stores.
+ *   use_graph: replay lb_step as captured two-step HIP graphs. */
+int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
+                  int32_t use_graph);
 
 void lb_destroy(lb_lattice* lat);
 const char* lb_strerror(int status);
 const char* lb_last_error(const lb_lattice* lat);
 int lb_abi_version(void);
+
+/* ------------------------------------------------------------------------
+ * Batches: n independent lattices (any sizes and couplings, one precision
+ * and boundary type) advanced together, one kernel launch per time step over
+ * the tiles of all of them.  Each lattice evolves exactly as it would alone:
+ * its fields are bit-for-bit those of an lb_lattice with the same parameters
+ * and initial state, and so are its observables.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_batch lb_batch;
+
+/* Device bytes for the batch (all lattices plus shared scratch). */
+int lb_batch_workspace_bytes(const lb_params* p /*[n]*/, int32_t n, size_t* out);
+/* p[i].device_buffer is ignored; device_buffer/device_bytes (optional, as in
+ * lb_params) cover the whole batch.  LB_E_INVAL if precisions or boundary
+ * types differ. */
+int lb_batch_create(const lb_params* p /*[n]*/, int32_t n, void* device_buffer,
+                    size_t device_bytes, void* hip_stream, lb_batch** out);
+int32_t lb_batch_size(const lb_batch* b);
+/* Per-lattice initial state (as lb_init / lb_init_noise), i in [0, n). */
+int lb_batch_init(lb_batch* b, int32_t i, const double* rho_a, const double* rho_b,
+                  const double* ux, const double* uy);
+int lb_batch_init_noise(lb_batch* b, int32_t i, uint64_t seed, double mean_a, double mean_b,
+                        double amp);
+/* Enqueue n steps of every lattice (LB_E_STATE until all are initialized). */
+int lb_batch_step(lb_batch* b, int64_t n);
+/* Observables of every lattice into out[0 .. n) (synchronizes). */
+int lb_batch_observables(lb_batch* b, lb_obs* out);
+int lb_batch_get_fields(lb_batch* b, int32_t i, double* rho_a, double* rho_b, double* u,
+                        double* u_phys);
+int lb_batch_get_populations(lb_batch* b, int32_t i, double* f);
+int lb_batch_sync(lb_batch* b);
+int lb_batch_get_launch_info(const lb_batch* b, lb_launch_info* out);
+/* As lb_set_launch without the segment height. */
+int lb_batch_set_launch(lb_batch* b, int32_t prefetch, int32_t stream_stores, int32_t use_graph);
+void lb_batch_destroy(lb_batch* b);
+const char* lb_batch_last_error(const lb_batch* b);
 
 #ifdef __cplusplus
 }

@@ -51,22 +51,34 @@ struct Coefs {
 struct Geometry {
   int nx, ny, pitch;
   long long row_elems;  // elements of one lattice row: (pitch / 64) blocks x 18 x 64
-  int nstrips, seg_h, nsegs, ntiles, tiles_per_xcd;
+  int nstrips, seg_h, nsegs, ntiles;  // tiles = strips x segments, one wavefront each
 };
 
-struct StepArgs {
-  const void* src;      // populations streamed into time t (pull layout)
-  void* dst;            // populations written for time t + 1
-  const void* wall_in;  // wall-link populations entering time t
-  void* wall_out;       // wall-link populations entering time t + 1
-  double* wave_red;     // observe: kNRed values per tile
-  double* wave_wall;    // step: 2 accumulators (bottom, top) per tile
-  double* fields;       // observe: [6][ny][nx] or null
-  double* pops;         // observe: [2][9][ny][nx] or null
-  int* flag;            // bit 0 set when a density is non-finite or <= 0
-  int accumulate_wall;  // step: add wall momentum to wave_wall
+// One lattice as the kernels see it (device memory, one record per lattice
+// of a launch; read with scalar loads).
+struct LatticeDesc {
   Geometry g;
   Coefs c;
+  void* buf[2];   // population buffers (pull layout)
+  void* wall[2];  // wall-link buffers
+  int* flag;      // bit 0 set when a density is non-finite or <= 0
+  int tile_base;  // first tile of this lattice in its launch's tile list
+  int phase;      // with launch step parity p the lattice reads buf[p ^ phase]
+};
+
+// Arguments of one step / observe launch over a set of lattices that share
+// precision and boundary type.
+struct LaunchArgs {
+  const LatticeDesc* descs;  // device array of the lattices
+  const int* tile_lattice;   // device array: lattice of each tile; null = all tiles are lattice 0
+  int ntiles;                // tiles in the launch
+  int tiles_per_xcd;         // ceil(ntiles / 8): tiles are handed out XCD-major
+  int parity;                // launch step parity
+  double* wave_red;          // observe: kNRed values per tile
+  double* wave_wall;         // step: 2 accumulators (bottom, top wall) per tile
+  double* fields;            // observe, single lattice: [6][ny][nx] or null
+  double* pops;              // observe, single lattice: [2][9][ny][nx] or null
+  int accumulate_wall;       // step: add wall momentum to wave_wall
 };
 
 // Code variants of the step kernel (tuning choices, same arithmetic).
@@ -76,12 +88,14 @@ struct StepVariant {
 };
 
 // Launchers (lb_kernels.hip).  All return hipError_t of the launch.
-hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, const StepVariant& v,
+hipError_t launch_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
                        hipStream_t st);
-hipError_t launch_observe(const StepArgs& a, bool fp64, bool walls, hipStream_t st);
-// Fixed-order sum of ntiles * width per-tile values into out[width].
-hipError_t launch_reduce_tiles(const double* in, int ntiles, int width, double* out,
-                               hipStream_t st);
+hipError_t launch_observe(const LaunchArgs& a, bool fp64, bool walls, hipStream_t st);
+// Fixed-order per-lattice sums: for lattice m of descs[0..n), the `width`
+// per-tile values of its tiles [tile_base, tile_base + ntiles) of `in` are
+// summed into out[m * out_stride + 0 .. width).
+hipError_t launch_reduce_lattices(const LatticeDesc* descs, int n, const double* in, int width,
+                                  double* out, int out_stride, hipStream_t st);
 // Write the t = 0 state: src buffer in pull layout plus the wall links, from
 // FP64 densities / velocities on the device (u may be null).
 hipError_t launch_init(const Geometry& g, const Coefs& c, bool fp64, bool walls,

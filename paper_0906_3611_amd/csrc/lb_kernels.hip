@@ -248,8 +248,18 @@ __host__ __device__ constexpr int pair_class(int m) {
 #ifndef LDS_GROUP
 #define LDS_GROUP 0
 #endif
+// Per-wave output context of a collision.
+template <typename ST>
+struct Out {
+  Geometry g;
+  ST* dst;        // populations for t + 1
+  ST* wall_out;   // wall links for t + 1
+  double* fields;  // observe outputs (single-lattice launches)
+  double* pops;
+};
+
 template <typename CT, bool DEV, bool WALLS, int MODE, typename ST, bool NT>
-__device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, DEV>& P,
+__device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, DEV>& P,
                                             const Fld<CT>* __restrict__ ring, int lc,
                                             const int (&slot)[5], int y, int col, uint32_t ob_c,
                                             const CT (&f)[2][9], double (&acc)[kNRed],
@@ -342,7 +352,7 @@ __device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, 
     return;
   }
 
-  ST* __restrict__ dst = (ST*)a.dst;
+  ST* __restrict__ dst = a.dst;
   double mom = 0;
   const bool wall_row = WALLS && (y == 0 || y == g.ny - 1);
   const int wl = (WALLS && y == g.ny - 1) ? 1 : 0;
@@ -367,7 +377,7 @@ __device__ __forceinline__ void collide_row(const StepArgs& a, const Params<CT, 
     }
     if (WALLS && wall_row) {
       const CT uwall = wl ? P.uw : -P.uw;
-      ST* wall_out = (ST*)a.wall_out;
+      ST* wall_out = a.wall_out;
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         // the j-th link leaves along o and returns as wall_in_dir:
@@ -402,16 +412,23 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // their shared ring rows at the same time and the second read hits L2.
 // PF = 1 issues the pull of the next row before the current collision.
 template <typename ST, typename CT, bool DEV, bool WALLS, int MODE, int PF, bool NT>
-__global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
+__global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
   constexpr int W = kWave + 4;
   constexpr int NSET = 3 + PF;
   __shared__ Fld<CT> ring[kRing * W];
-  const Geometry& g = a.g;
   const int b = blockIdx.x;
-  const int tile = (b & 7) * g.tiles_per_xcd + (b >> 3);
-  if (tile >= g.ntiles) return;
-  const int strip = tile % g.nstrips;
-  const int seg = tile / g.nstrips;
+  const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
+  if (tile >= a.ntiles) return;
+  // the lattice of this tile and its record (uniform: scalar loads)
+  const int li = a.tile_lattice ? a.tile_lattice[tile] : 0;
+  const LatticeDesc* __restrict__ D = a.descs + li;
+  const Geometry g = D->g;
+  // batch launches number tiles across lattices; single-lattice launches
+  // (tile_lattice null) number the lattice's own tiles from 0
+  const int local = a.tile_lattice ? tile - D->tile_base : tile;
+  const int sel = (a.parity ^ D->phase) & 1;
+  const int strip = local % g.nstrips;
+  const int seg = local / g.nstrips;
   const int lane = threadIdx.x;
   const int nx = g.nx, ny = g.ny;
   const int x0 = strip * kWave;
@@ -435,9 +452,10 @@ __global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
   const uint32_t rb_m = in_row(rcol == 0 ? nx - 1 : rcol - 1);
   const uint32_t rb_p = in_row(rcol == nx - 1 ? 0 : rcol + 1);
 
-  const Params<CT, DEV> P(a.c);
-  const ST* __restrict__ src = (const ST*)a.src;
-  const ST* __restrict__ wall_in = (const ST*)a.wall_in;
+  const Params<CT, DEV> P(D->c);
+  const ST* __restrict__ src = (const ST*)D->buf[sel];
+  const ST* __restrict__ wall_in = (const ST*)D->wall[sel];
+  const Out<ST> out{g, (ST*)D->buf[sel ^ 1], (ST*)D->wall[sel ^ 1], a.fields, a.pops};
 
   CT fr[NSET][2][9];
   CT rg[2][9];
@@ -482,13 +500,13 @@ __global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
 #pragma unroll
         for (int d = 0; d < 5; ++d) slot[d] = (k - 2 + dir * (d - 2)) % kRing;
         const int y = lattice_row(k - 2);
-        collide_row<CT, DEV, WALLS, MODE, ST, NT>(a, P, ring, lane + 2, slot, y, col, ob_c,
+        collide_row<CT, DEV, WALLS, MODE, ST, NT>(out, P, ring, lane + 2, slot, y, col, ob_c,
                                               fr[(j + NSET - 2) % NSET], acc, wacc, bad);
       }
     });
   }
 
-  if (__any(bad) && lane == 0) atomicOr(a.flag, 1);
+  if (__any(bad) && lane == 0) atomicOr(D->flag, 1);
   if (MODE == kObserve) {
 #pragma unroll
     for (int m = 0; m < kNRed; ++m) {
@@ -508,21 +526,26 @@ __global__ __launch_bounds__(kWave) void k_march(const StepArgs a) {
   }
 }
 
-// Fixed-order reduction of per-tile values: thread t sums tiles t, t + 256,
-// ... in order, then a fixed binary tree.  One block; deterministic.
-__global__ __launch_bounds__(256) void k_reduce_tiles(const double* __restrict__ in, int ntiles,
-                                                      int width, double* __restrict__ out) {
+// Fixed-order reduction of per-tile values, one workgroup per lattice:
+// thread t sums the lattice's tiles t, t + 256, ... in order, then a fixed
+// binary tree.  The result depends only on the lattice's own tiles, so it is
+// the same bit for bit whether the lattice ran alone or in a batch.
+__global__ __launch_bounds__(256) void k_reduce_lattices(const LatticeDesc* __restrict__ descs,
+                                                         const double* __restrict__ in, int width,
+                                                         double* __restrict__ out, int out_stride) {
   __shared__ double sh[256];
+  const LatticeDesc* D = descs + blockIdx.x;
+  const int base = D->tile_base, ntiles = D->g.ntiles;
   for (int m = 0; m < width; ++m) {
     double v = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += 256) v += in[(long long)t * width + m];
+    for (int t = threadIdx.x; t < ntiles; t += 256) v += in[(long long)(base + t) * width + m];
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int h = 128; h >= 1; h >>= 1) {
       if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
       __syncthreads();
     }
-    if (threadIdx.x == 0) out[m] = sh[0];
+    if (threadIdx.x == 0) out[(long long)blockIdx.x * out_stride + m] = sh[0];
     __syncthreads();
   }
 }
@@ -597,8 +620,8 @@ __global__ __launch_bounds__(256) void k_noise(int nx, int ny, uint64_t seed, do
 }
 
 template <int MODE, int PF, bool NT>
-hipError_t launch_march(const StepArgs& a, bool fp64, bool walls, hipStream_t st) {
-  const dim3 grid(8 * a.g.tiles_per_xcd), block(kWave);
+hipError_t launch_march(const LaunchArgs& a, bool fp64, bool walls, hipStream_t st) {
+  const dim3 grid(8 * a.tiles_per_xcd), block(kWave);
   if (fp64) {
     if (walls)
       hipLaunchKernelGGL((k_march<double, double, false, true, MODE, PF, NT>), grid, block, 0, st, a);
@@ -645,7 +668,7 @@ hipError_t launch_init_any(const Geometry& g, const Coefs& c, bool fp64, bool wa
 
 }  // namespace
 
-hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, const StepVariant& v,
+hipError_t launch_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
                        hipStream_t st) {
   if (v.prefetch)
     return v.stream_stores ? launch_march<kStep, 1, true>(a, fp64, walls, st)
@@ -654,13 +677,14 @@ hipError_t launch_step(const StepArgs& a, bool fp64, bool walls, const StepVaria
                          : launch_march<kStep, 0, false>(a, fp64, walls, st);
 }
 
-hipError_t launch_observe(const StepArgs& a, bool fp64, bool walls, hipStream_t st) {
+hipError_t launch_observe(const LaunchArgs& a, bool fp64, bool walls, hipStream_t st) {
   return launch_march<kObserve, 0, false>(a, fp64, walls, st);
 }
 
-hipError_t launch_reduce_tiles(const double* in, int ntiles, int width, double* out,
-                               hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_tiles, dim3(1), dim3(256), 0, st, in, ntiles, width, out);
+hipError_t launch_reduce_lattices(const LatticeDesc* descs, int n, const double* in, int width,
+                                  double* out, int out_stride, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reduce_lattices, dim3(n), dim3(256), 0, st, descs, in, width, out, out_stride);
   return hipGetLastError();
 }
 

@@ -4,7 +4,7 @@ Every step of the lattice Boltzmann update runs in the library's HIP
 kernels.  PyTorch supplies the device workspace (a uint8 CUDA tensor) and
 the HIP stream (torch's current stream), so library work interleaves with
 torch work and torch's events can time it.  If the compiled library is
-missing this module raises at import-time use; there is no CPU fallback.
+missing, load() raises; there is no CPU fallback.
 """
 from __future__ import annotations
 
@@ -48,7 +48,9 @@ class lb_launch_info(ctypes.Structure):
     _fields_ = [("nstrips", ctypes.c_int32), ("nsegs", ctypes.c_int32), ("ntiles", ctypes.c_int32),
                 ("grid_blocks", ctypes.c_int32), ("block_threads", ctypes.c_int32),
                 ("pitch", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
-                ("population_bytes", ctypes.c_size_t)]
+                ("population_bytes", ctypes.c_size_t), ("seg_h", ctypes.c_int32),
+                ("prefetch", ctypes.c_int32), ("stream_stores", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
 
 
 _lib = None
@@ -64,27 +66,43 @@ def load():
                           "(run __graft_entry__.build())")
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
-    vp, dp, i64 = ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64
-    lat = ctypes.c_void_p
+    vp, dp, i64, i32 = ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64, ctypes.c_int32
+    h = ctypes.c_void_p
     sig = {
         "lb_abi_version": ([], ctypes.c_int),
         "lb_strerror": ([ctypes.c_int], ctypes.c_char_p),
-        "lb_last_error": ([lat], ctypes.c_char_p),
+        "lb_last_error": ([h], ctypes.c_char_p),
         "lb_workspace_bytes": ([P(lb_params), P(ctypes.c_size_t)], ctypes.c_int),
-        "lb_create": ([P(lb_params), vp, P(lat)], ctypes.c_int),
-        "lb_init": ([lat, dp, dp, dp, dp], ctypes.c_int),
-        "lb_init_noise": ([lat, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double],
+        "lb_create": ([P(lb_params), vp, P(h)], ctypes.c_int),
+        "lb_init": ([h, dp, dp, dp, dp], ctypes.c_int),
+        "lb_init_noise": ([h, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double],
                           ctypes.c_int),
-        "lb_step": ([lat, i64], ctypes.c_int),
-        "lb_observables": ([lat, P(lb_obs)], ctypes.c_int),
-        "lb_get_fields": ([lat, dp, dp, dp, dp], ctypes.c_int),
-        "lb_get_populations": ([lat, dp], ctypes.c_int),
-        "lb_set_populations": ([lat, dp, i64], ctypes.c_int),
-        "lb_reset_averages": ([lat], ctypes.c_int),
-        "lb_sync": ([lat], ctypes.c_int),
-        "lb_current_step": ([lat], i64),
-        "lb_get_launch_info": ([lat, P(lb_launch_info)], ctypes.c_int),
-        "lb_destroy": ([lat], None),
+        "lb_step": ([h, i64], ctypes.c_int),
+        "lb_observables": ([h, P(lb_obs)], ctypes.c_int),
+        "lb_get_fields": ([h, dp, dp, dp, dp], ctypes.c_int),
+        "lb_get_populations": ([h, dp], ctypes.c_int),
+        "lb_set_populations": ([h, dp, i64], ctypes.c_int),
+        "lb_reset_averages": ([h], ctypes.c_int),
+        "lb_sync": ([h], ctypes.c_int),
+        "lb_current_step": ([h], i64),
+        "lb_get_launch_info": ([h, P(lb_launch_info)], ctypes.c_int),
+        "lb_set_launch": ([h, i32, i32, i32, i32], ctypes.c_int),
+        "lb_destroy": ([h], None),
+        "lb_batch_workspace_bytes": ([P(lb_params), i32, P(ctypes.c_size_t)], ctypes.c_int),
+        "lb_batch_create": ([P(lb_params), i32, vp, ctypes.c_size_t, vp, P(h)], ctypes.c_int),
+        "lb_batch_size": ([h], i32),
+        "lb_batch_init": ([h, i32, dp, dp, dp, dp], ctypes.c_int),
+        "lb_batch_init_noise": ([h, i32, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double], ctypes.c_int),
+        "lb_batch_step": ([h, i64], ctypes.c_int),
+        "lb_batch_observables": ([h, P(lb_obs)], ctypes.c_int),
+        "lb_batch_get_fields": ([h, i32, dp, dp, dp, dp], ctypes.c_int),
+        "lb_batch_get_populations": ([h, i32, dp], ctypes.c_int),
+        "lb_batch_sync": ([h], ctypes.c_int),
+        "lb_batch_get_launch_info": ([h, P(lb_launch_info)], ctypes.c_int),
+        "lb_batch_set_launch": ([h, i32, i32, i32], ctypes.c_int),
+        "lb_batch_destroy": ([h], None),
+        "lb_batch_last_error": ([h], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -114,61 +132,55 @@ def _f64(a, shape):
     return a
 
 
-class Lattice:
-    """One two-species lattice on the current GPU.
+def make_params(nx, ny, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1),
+                G_AB=0.405, boundary="periodic", u_wall=0.0, precision="fp64",
+                rho_ref=(0.0, 0.0)) -> lb_params:
+    """An lb_params record (parameters of Sec. II, Eqs. (1), (2), (5))."""
+    p = lb_params()
+    p.nx, p.ny = int(nx), int(ny)
+    p.boundary = {"periodic": LB_PERIODIC, "couette": LB_COUETTE_Y}[boundary]
+    p.precision = {"fp64": LB_FP64, "fp32dev": LB_FP32_DEV}[precision]
+    p.tau[0], p.tau[1] = tau
+    p.rho0 = rho0
+    p.G_a[0], p.G_a[1] = G_a
+    p.G_r[0], p.G_r[1] = G_r
+    p.G_AB = G_AB
+    p.u_wall = u_wall
+    p.rho_ref[0], p.rho_ref[1] = rho_ref
+    return p
 
-    precision: "fp64" or "fp32dev"; boundary: "periodic" or "couette".
-    With use_torch (default) the device workspace is a torch uint8 tensor and
-    work runs on torch's current stream; otherwise the library allocates and
-    uses the null stream.
-    """
 
-    def __init__(self, nx: int, ny: int, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0),
-                 G_r=(8.1, 8.1), G_AB=0.405, boundary="periodic", u_wall=0.0, precision="fp64",
-                 rho_ref=(0.0, 0.0), use_torch=True, stream=None):
-        self._lib = load()
-        self._h = ctypes.c_void_p()
-        self.nx, self.ny = int(nx), int(ny)
-        p = lb_params()
-        p.nx, p.ny = self.nx, self.ny
-        p.boundary = {"periodic": LB_PERIODIC, "couette": LB_COUETTE_Y}[boundary]
-        p.precision = {"fp64": LB_FP64, "fp32dev": LB_FP32_DEV}[precision]
-        p.tau[0], p.tau[1] = tau
-        p.rho0 = rho0
-        p.G_a[0], p.G_a[1] = G_a
-        p.G_r[0], p.G_r[1] = G_r
-        p.G_AB = G_AB
-        p.u_wall = u_wall
-        p.rho_ref[0], p.rho_ref[1] = rho_ref
-        self.precision, self.boundary = precision, boundary
-        nbytes = ctypes.c_size_t()
-        self._check(self._lib.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)), "workspace")
-        self._buf = None
-        sptr = None
-        if use_torch:
-            import torch
-            self._buf = torch.empty(int(nbytes.value), dtype=torch.uint8, device="cuda")
-            p.device_buffer = self._buf.data_ptr()
-            p.device_bytes = int(nbytes.value)
-            self.stream = torch.cuda.current_stream() if stream is None else stream
-            sptr = self.stream.cuda_stream
-        else:
-            self.stream = stream
-            sptr = None if stream is None else int(stream)
-        self._check(self._lib.lb_create(ctypes.byref(p), sptr, ctypes.byref(self._h)), "lb_create")
-        self.params = p
+def _obs_dict(o) -> dict:
+    return {"step": o.step, "mass": np.array(o.mass[:]), "mom": np.array(o.mom[:]),
+            "mom_phys": np.array(o.mom_phys[:]), "pxy_kin": o.pxy_kin,
+            "wall_stress": np.array(o.wall_stress[:]), "avg_count": o.avg_count,
+            "flags": o.flags}
 
-    # -- plumbing ---------------------------------------------------------
+
+def _info_dict(li) -> dict:
+    return {k: getattr(li, k) for k, _ in lb_launch_info._fields_}
+
+
+def _torch_workspace(nbytes):
+    import torch
+    buf = torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+    return buf, torch.cuda.current_stream()
+
+
+class _Handle:
+    _destroy = ""
+    _last_error = ""
+
     def _check(self, rc, what):
         if rc != LB_OK:
             msg = ""
             if getattr(self, "_h", None) and self._h.value:
-                msg = (self._lib.lb_last_error(self._h) or b"").decode()
+                msg = (getattr(self._lib, self._last_error)(self._h) or b"").decode()
             raise LBError(rc, f"{what}: {self._lib.lb_strerror(rc).decode()}: {msg}")
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
-            self._lib.lb_destroy(self._h)
+            getattr(self._lib, self._destroy)(self._h)
             self._h = ctypes.c_void_p()
         self._buf = None
 
@@ -184,7 +196,42 @@ class Lattice:
     def __exit__(self, *exc):
         self.close()
 
-    # -- API ----------------------------------------------------------------
+
+class Lattice(_Handle):
+    """One two-species lattice on the current GPU.
+
+    precision: "fp64" or "fp32dev"; boundary: "periodic" or "couette".
+    With use_torch (default) the device workspace is a torch uint8 tensor and
+    work runs on torch's current stream; otherwise the library allocates and
+    uses the null stream.
+    """
+    _destroy = "lb_destroy"
+    _last_error = "lb_last_error"
+
+    def __init__(self, nx: int, ny: int, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0),
+                 G_r=(8.1, 8.1), G_AB=0.405, boundary="periodic", u_wall=0.0, precision="fp64",
+                 rho_ref=(0.0, 0.0), use_torch=True, stream=None):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        self.nx, self.ny = int(nx), int(ny)
+        p = make_params(nx, ny, tau=tau, rho0=rho0, G_a=G_a, G_r=G_r, G_AB=G_AB, boundary=boundary,
+                        u_wall=u_wall, precision=precision, rho_ref=rho_ref)
+        self.precision, self.boundary = precision, boundary
+        nbytes = ctypes.c_size_t()
+        self._check(self._lib.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)), "workspace")
+        self._buf = None
+        if use_torch:
+            self._buf, cur = _torch_workspace(nbytes.value)
+            p.device_buffer = self._buf.data_ptr()
+            p.device_bytes = int(nbytes.value)
+            self.stream = cur if stream is None else stream
+            sptr = self.stream.cuda_stream
+        else:
+            self.stream = stream
+            sptr = None if stream is None else int(stream)
+        self._check(self._lib.lb_create(ctypes.byref(p), sptr, ctypes.byref(self._h)), "lb_create")
+        self.params = p
+
     def init(self, rho_a, rho_b, ux=None, uy=None):
         shp = (self.ny, self.nx)
         ra, rb = _f64(rho_a, shp), _f64(rho_b, shp)
@@ -206,10 +253,7 @@ class Lattice:
     def observables(self) -> dict:
         o = lb_obs()
         self._check(self._lib.lb_observables(self._h, ctypes.byref(o)), "lb_observables")
-        return {"step": o.step, "mass": np.array(o.mass[:]), "mom": np.array(o.mom[:]),
-                "mom_phys": np.array(o.mom_phys[:]), "pxy_kin": o.pxy_kin,
-                "wall_stress": np.array(o.wall_stress[:]), "avg_count": o.avg_count,
-                "flags": o.flags}
+        return _obs_dict(o)
 
     def fields(self) -> dict:
         ny, nx = self.ny, self.nx
@@ -237,4 +281,90 @@ class Lattice:
     def launch_info(self) -> dict:
         li = lb_launch_info()
         self._check(self._lib.lb_get_launch_info(self._h, ctypes.byref(li)), "lb_get_launch_info")
-        return {k: getattr(li, k) for k, _ in lb_launch_info._fields_}
+        return _info_dict(li)
+
+    def set_launch(self, seg_h=-1, prefetch=-1, stream_stores=-1, use_graph=-1):
+        """Tuning knobs (lb_set_launch); -1 keeps the current choice."""
+        self._check(self._lib.lb_set_launch(self._h, int(seg_h), int(prefetch), int(stream_stores),
+                                            int(use_graph)), "lb_set_launch")
+
+
+class Batch(_Handle):
+    """Independent lattices advanced by one kernel launch per step.
+
+    specs: a list of keyword dicts for make_params (each with nx and ny), all
+    of one precision and boundary type."""
+    _destroy = "lb_batch_destroy"
+    _last_error = "lb_batch_last_error"
+
+    def __init__(self, specs, use_torch=True, stream=None):
+        self._lib = load()
+        self._h = ctypes.c_void_p()
+        n = len(specs)
+        arr = (lb_params * n)()
+        self.shapes = []
+        for i, sp in enumerate(specs):
+            sp = dict(sp)
+            nx, ny = sp.pop("nx"), sp.pop("ny")
+            arr[i] = make_params(nx, ny, **sp)
+            self.shapes.append((int(ny), int(nx)))
+        self.n = n
+        nbytes = ctypes.c_size_t()
+        self._check(self._lib.lb_batch_workspace_bytes(arr, n, ctypes.byref(nbytes)), "workspace")
+        self._buf = None
+        if use_torch:
+            self._buf, cur = _torch_workspace(nbytes.value)
+            self.stream = cur if stream is None else stream
+            bptr, sptr = self._buf.data_ptr(), self.stream.cuda_stream
+        else:
+            self.stream, bptr, sptr = stream, None, (None if stream is None else int(stream))
+        self._check(self._lib.lb_batch_create(arr, n, bptr, int(nbytes.value), sptr,
+                                              ctypes.byref(self._h)), "lb_batch_create")
+
+    def init(self, i, rho_a, rho_b, ux=None, uy=None):
+        shp = self.shapes[i]
+        ra, rb = _f64(rho_a, shp), _f64(rho_b, shp)
+        vx = None if ux is None else _f64(ux, shp)
+        vy = None if uy is None else _f64(uy, shp)
+        self._check(self._lib.lb_batch_init(self._h, int(i), _dptr(ra), _dptr(rb), _dptr(vx),
+                                            _dptr(vy)), "lb_batch_init")
+
+    def init_noise(self, i, seed, mean_a, mean_b, amp):
+        self._check(self._lib.lb_batch_init_noise(self._h, int(i), int(seed), float(mean_a),
+                                                  float(mean_b), float(amp)), "lb_batch_init_noise")
+
+    def step(self, n=1):
+        self._check(self._lib.lb_batch_step(self._h, int(n)), "lb_batch_step")
+
+    def observables(self) -> list:
+        arr = (lb_obs * self.n)()
+        self._check(self._lib.lb_batch_observables(self._h, arr), "lb_batch_observables")
+        return [_obs_dict(o) for o in arr]
+
+    def fields(self, i) -> dict:
+        ny, nx = self.shapes[i]
+        ra, rb = np.empty((ny, nx)), np.empty((ny, nx))
+        u, up = np.empty((2, ny, nx)), np.empty((2, ny, nx))
+        self._check(self._lib.lb_batch_get_fields(self._h, int(i), _dptr(ra), _dptr(rb), _dptr(u),
+                                                  _dptr(up)), "lb_batch_get_fields")
+        return {"rho": np.stack([ra, rb]), "u": u, "uphys": up}
+
+    def populations(self, i) -> np.ndarray:
+        ny, nx = self.shapes[i]
+        f = np.empty((2, 9, ny, nx))
+        self._check(self._lib.lb_batch_get_populations(self._h, int(i), _dptr(f)),
+                    "lb_batch_get_populations")
+        return f
+
+    def sync(self):
+        self._check(self._lib.lb_batch_sync(self._h), "lb_batch_sync")
+
+    def launch_info(self) -> dict:
+        li = lb_launch_info()
+        self._check(self._lib.lb_batch_get_launch_info(self._h, ctypes.byref(li)),
+                    "lb_batch_get_launch_info")
+        return _info_dict(li)
+
+    def set_launch(self, prefetch=-1, stream_stores=-1, use_graph=-1):
+        self._check(self._lib.lb_batch_set_launch(self._h, int(prefetch), int(stream_stores),
+                                                  int(use_graph)), "lb_batch_set_launch")

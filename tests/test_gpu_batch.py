@@ -1,0 +1,139 @@
+"""Batched lattices, graph replay and launch variants through the C ABI.
+
+A lattice advanced inside a batch, by replayed HIP graphs, or with any
+tuning variant (segment height, prefetch, streaming stores) must produce the
+same fields bit for bit as the plain single-lattice path: the per-site
+arithmetic does not depend on tiling or launch mode.  Observable reductions
+are fixed-order per lattice, so they agree bit for bit as well when the
+lattice keeps its tiling.
+"""
+import numpy as np
+import pytest
+import torch  # noqa: F401  (first import can be slow; keep it out of test timeouts)
+
+from paper_0906_3611_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405)
+
+
+def _lb():
+    from paper_0906_3611_amd import lb
+    return lb
+
+
+def _specs(precision, boundary):
+    u = 0.01 if boundary == "couette" else 0.0
+    s = []
+    for nx, ny, ga in ((67, 45, -9.0), (130, 70, -8.5), (64, 64, -9.3), (5, 9, -9.0)):
+        d = dict(BASE)
+        d.update(nx=nx, ny=ny, G_a=(ga, ga), precision=precision, boundary=boundary, u_wall=u)
+        s.append(d)
+    return s
+
+
+def _fields_of(spec, seed):
+    return inputs.noise_fields(spec["nx"], spec["ny"], seed, 0.5, 0.5, 0.05)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+@pytest.mark.parametrize("boundary", ["periodic", "couette"])
+def test_batch_matches_single_bitwise(precision, boundary):
+    lb = _lb()
+    specs = _specs(precision, boundary)
+    b = lb.Batch(specs)
+    singles = []
+    for i, sp in enumerate(specs):
+        ra, rb = _fields_of(sp, 100 + i)
+        b.init(i, ra, rb)
+        kw = dict(sp)
+        nx, ny = kw.pop("nx"), kw.pop("ny")
+        lat = lb.Lattice(nx, ny, **kw)
+        lat.init(ra, rb)
+        singles.append(lat)
+    b.step(13)
+    for lat in singles:
+        lat.step(13)
+    obs_b = b.observables()
+    for i, lat in enumerate(singles):
+        assert np.array_equal(b.populations(i), lat.populations()), i
+        o = lat.observables()
+        assert np.array_equal(obs_b[i]["mass"], o["mass"]), i
+        assert np.array_equal(obs_b[i]["mom"], o["mom"]), i
+        assert obs_b[i]["pxy_kin"] == o["pxy_kin"], i
+        assert np.array_equal(obs_b[i]["wall_stress"], o["wall_stress"]), i
+        assert obs_b[i]["step"] == 13
+    info = b.launch_info()
+    assert info["ntiles"] == sum(l.launch_info()["ntiles"] for l in singles)
+
+
+def test_batch_rejects_mixed_precision_and_uninitialized_step():
+    lb = _lb()
+    specs = _specs("fp64", "periodic")
+    specs[1] = dict(specs[1], precision="fp32dev")
+    with pytest.raises(lb.LBError) as ei:
+        lb.Batch(specs)
+    assert ei.value.code == lb.LB_E_INVAL
+    b = lb.Batch(_specs("fp64", "periodic"))
+    b.init_noise(0, 1, 0.5, 0.5, 0.01)
+    with pytest.raises(lb.LBError) as ei:
+        b.step(1)
+    assert ei.value.code == lb.LB_E_STATE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_graph_replays_match_eager(precision):
+    """Two-step graphs replayed several times, with eager work and
+    synchronizations between the replays, against plain launches."""
+    lb = _lb()
+    nx, ny = 70, 48
+    ra, rb = inputs.noise_fields(nx, ny, 3, 0.5, 0.5, 0.05)
+    eager = lb.Lattice(nx, ny, precision=precision, **BASE)
+    graph = lb.Lattice(nx, ny, precision=precision, **BASE)
+    graph.set_launch(use_graph=1)
+    assert graph.launch_info()["use_graph"] == 1
+    for lat in (eager, graph):
+        lat.init(ra, rb)
+    for n in (2, 4, 3, 6, 1, 2):  # odd counts leave the graph parity changed
+        eager.step(n)
+        graph.step(n)
+        o1, o2 = eager.observables(), graph.observables()  # eager work between replays
+        assert np.array_equal(o1["mass"], o2["mass"])
+        assert np.array_equal(eager.populations(), graph.populations()), n
+    assert graph.t == eager.t == 18
+
+
+def test_batch_graph_matches_batch_eager():
+    lb = _lb()
+    specs = _specs("fp32dev", "periodic")
+    a, b = lb.Batch(specs), lb.Batch(specs)
+    b.set_launch(use_graph=1)
+    for i, sp in enumerate(specs):
+        ra, rb = _fields_of(sp, 7 + i)
+        a.init(i, ra, rb)
+        b.init(i, ra, rb)
+    for n in (4, 2, 5):
+        a.step(n)
+        b.step(n)
+        for i in range(len(specs)):
+            assert np.array_equal(a.populations(i), b.populations(i))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_launch_variants_do_not_change_fields(precision):
+    lb = _lb()
+    nx, ny = 200, 96
+    ra, rb = inputs.noise_fields(nx, ny, 9, 0.5, 0.5, 0.05)
+    ref = lb.Lattice(nx, ny, precision=precision, **BASE)
+    ref.init(ra, rb)
+    ref.step(11)
+    f_ref = ref.populations()
+    for seg_h, pf, nt in ((4, 0, 0), (8, 1, 1), (33, 0, 1), (96, 1, 0)):
+        lat = lb.Lattice(nx, ny, precision=precision, **BASE)
+        lat.set_launch(seg_h=seg_h, prefetch=pf, stream_stores=nt)
+        info = lat.launch_info()
+        assert (info["prefetch"], info["stream_stores"]) == (pf, nt)
+        lat.init(ra, rb)
+        lat.step(11)
+        assert np.array_equal(lat.populations(), f_ref), (seg_h, pf, nt)
