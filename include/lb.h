@@ -213,6 +213,58 @@ int lb_batch_set_launch(lb_batch* b, int32_t prefetch, int32_t stream_stores, in
 void lb_batch_destroy(lb_batch* b);
 const char* lb_batch_last_error(const lb_batch* b);
 
+/* ------------------------------------------------------------------------
+ * Serving pool: simulation jobs (one lattice each) are admitted in arrival
+ * order while their device footprint fits an HBM budget (a job that does not
+ * fit yet does not block later, smaller ones), kept resident, and advanced
+ * together: every lb_pool_advance step is one launch per class of
+ * (precision, boundary type) over all resident jobs of that class.  A job
+ * stops exactly at its own step count; it is then retired: its observables
+ * (and, unless switched off, its density fields) are copied to the host and
+ * its device memory is released.  Times are seconds since lb_pool_create on
+ * a monotonic host clock.  Not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_pool lb_pool;
+enum { LB_JOB_QUEUED = 0, LB_JOB_RUNNING = 1, LB_JOB_DONE = 2, LB_JOB_FAILED = 3 };
+
+typedef struct {
+  int64_t submitted, queued, running, done, failed;
+  size_t resident_bytes, budget_bytes;
+  int64_t site_updates;  /* completed site updates, summed over jobs */
+  int64_t ticks;         /* launch rounds (steps between membership changes) */
+  int64_t steps;         /* pool steps run */
+  double clock;          /* seconds since creation */
+} lb_pool_stats;
+
+/* hbm_budget_bytes: ceiling on the summed device footprint of resident jobs. */
+int lb_pool_create(size_t hbm_budget_bytes, void* hip_stream, lb_pool** out);
+void lb_pool_destroy(lb_pool* pool);
+const char* lb_pool_last_error(const lb_pool* pool);
+/* keep_fields: copy final densities at retirement (default 1); use_graph:
+ * replay step pairs as HIP graphs (default 1).  < 0 keeps the setting. */
+int lb_pool_set_options(lb_pool* pool, int32_t keep_fields, int32_t use_graph);
+/* Device footprint of one job with these parameters (0 if invalid). */
+size_t lb_pool_job_bytes(const lb_params* p);
+/* Queue a job of `steps` steps (p->device_buffer ignored), started from the
+ * lb_init_noise state or from host densities (copied at submission).
+ * LB_E_NOMEM if its footprint alone exceeds the budget. */
+int lb_pool_submit_noise(lb_pool* pool, const lb_params* p, uint64_t seed, double mean_a,
+                         double mean_b, double amp, int64_t steps, int64_t* job_id);
+int lb_pool_submit(lb_pool* pool, const lb_params* p, const double* rho_a, const double* rho_b,
+                   int64_t steps, int64_t* job_id);
+/* Admit what fits, run n pool steps (jobs finish at their own counts),
+ * retire finished jobs, admit again as memory frees.  Synchronizes. */
+int lb_pool_advance(lb_pool* pool, int64_t n);
+int lb_pool_job_state(const lb_pool* pool, int64_t job_id, int32_t* state);
+/* Result of a finished job: observables, densities [ny][nx] (each may be
+ * NULL) and times[3] = {submitted, admitted, done} (may be NULL; filled for
+ * any job).  LB_E_STATE if not finished; the failure status if it failed. */
+int lb_pool_job_result(lb_pool* pool, int64_t job_id, lb_obs* obs, double* rho_a, double* rho_b,
+                       double* times);
+/* Forget a finished job (frees its host copies). */
+int lb_pool_release(lb_pool* pool, int64_t job_id);
+int lb_pool_get_stats(const lb_pool* pool, lb_pool_stats* out);
+
 #ifdef __cplusplus
 }
 #endif

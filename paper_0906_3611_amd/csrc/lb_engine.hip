@@ -1,0 +1,753 @@
+// Engine: lattices of one precision and boundary type advancing together,
+// one step launch over the tiles of all of them (see lb_engine.h).
+#include "lb_engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+
+namespace lbe {
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Weights of the interaction lattice (Table I): w on the first belt,
+// p on both belts, by class |c|^2 = 1, 2, 4, 5, 8.
+constexpr double kW1 = 1.0 / 9.0, kW2 = 1.0 / 36.0;
+constexpr double kP1 = 4.0 / 63.0, kP2 = 4.0 / 135.0, kP4 = 1.0 / 180.0, kP5 = 2.0 / 945.0,
+                 kP8 = 1.0 / 15120.0;
+constexpr size_t kInfinityCacheBytes = 256ull << 20;
+
+bool is_finite(double v) { return std::isfinite(v); }
+
+// Tiles: 64-column strips x row segments.  Aim for about 2048 wavefronts
+// (8 per CU) with segments of 8..64 rows: fewer, taller segments re-read
+// fewer ring rows, more keep HBM busy.  seg_h > 0 forces the segment height.
+lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
+  lbk::Geometry g{};
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.pitch = (p->nx + lbk::kWave - 1) / lbk::kWave * lbk::kWave;  // strips start on a line
+  g.row_elems = (long long)(g.pitch / lbk::kWave) * 18 * lbk::kWave;
+  g.nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
+  int nsegs = (2048 + g.nstrips - 1) / g.nstrips;
+  nsegs = std::min(nsegs, std::max(1, p->ny / 8));
+  nsegs = std::max(nsegs, (p->ny + 63) / 64);
+  if (seg_h <= 0) {
+    if (const char* e = std::getenv("LBSOFT_SEG_H")) seg_h = std::atoi(e);
+  }
+  if (seg_h >= 4) nsegs = (p->ny + seg_h - 1) / seg_h;
+  nsegs = std::max(1, std::min(nsegs, p->ny));
+  g.nsegs = nsegs;
+  g.seg_h = (p->ny + nsegs - 1) / nsegs;
+  g.ntiles = g.nstrips * g.nsegs;
+  return g;
+}
+
+// The most tiles any segment height >= 4 can give (sizes the per-tile slots).
+int max_tiles_of(const lb_params* p) {
+  const int nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
+  const int nsegs = std::max(1, std::min(p->ny, (p->ny + 3) / 4));
+  return std::max(nstrips * nsegs, make_geometry(p, 0).ntiles);
+}
+
+size_t elem_size(const lb_params* p) { return p->precision == LB_FP64 ? 8 : 4; }
+
+// Derived reference values and FP32 copies of the constants for the FP32
+// kernels.  rho_ref is first rounded to FP32 so both precisions of the
+// kernels see the same reference.
+void round_coefs(lbk::Coefs& c) {
+  for (int s = 0; s < 2; ++s) {
+    c.rho_ref[s] = (double)(float)c.rho_ref[s];
+    c.psi_ref[s] = c.rho0 * -std::expm1(-c.rho_ref[s] / c.rho0);
+    c.psi_scale[s] = c.rho0 * std::exp(-c.rho_ref[s] / c.rho0);
+    c.f_psi_ref[s] = (float)c.psi_ref[s];
+    c.f_psi_scale[s] = (float)c.psi_scale[s];
+    for (int m = 0; m < 5; ++m) c.f_kself[s][m] = (float)c.kself[s][m];
+    c.f_tau[s] = (float)c.tau[s];
+    c.f_omega[s] = (float)c.omega[s];
+    c.f_rho_ref[s] = (float)c.rho_ref[s];
+  }
+  c.f_kcross[0] = (float)c.kcross[0];
+  c.f_kcross[1] = (float)c.kcross[1];
+  c.f_rho0 = (float)c.rho0;
+  c.f_inv_rho0 = (float)c.inv_rho0;
+  c.f_u_wall = (float)c.u_wall;
+}
+
+lbk::Coefs make_coefs(const lb_params* p) {
+  lbk::Coefs c{};
+  for (int s = 0; s < 2; ++s) {
+    c.kself[s][0] = p->G_a[s] * kW1 + p->G_r[s] * kP1;
+    c.kself[s][1] = p->G_a[s] * kW2 + p->G_r[s] * kP2;
+    c.kself[s][2] = p->G_r[s] * kP4;
+    c.kself[s][3] = p->G_r[s] * kP5;
+    c.kself[s][4] = p->G_r[s] * kP8;
+    c.tau[s] = p->tau[s];
+    c.omega[s] = 1.0 / p->tau[s];
+    c.rho_ref[s] = p->rho_ref[s] > 0 ? p->rho_ref[s] : 1.0;
+  }
+  const double g = p->G_AB / (p->rho0 * p->rho0);
+  c.kcross[0] = g * kW1;
+  c.kcross[1] = g * kW2;
+  c.rho0 = p->rho0;
+  c.inv_rho0 = 1.0 / p->rho0;
+  c.u_wall = p->u_wall;
+  round_coefs(c);
+  return c;
+}
+
+// Temporary device array freed at scope exit.
+struct DevTmp {
+  void* p = nullptr;
+  ~DevTmp() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+#define HIPCK(E, expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return (E).fail(LB_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t shared_bytes(int cap_members, int cap_tiles) {
+  return align_up((size_t)cap_members * sizeof(lbk::LatticeDesc)) +
+         align_up((size_t)cap_tiles * sizeof(int)) + align_up((size_t)cap_members * 16 * sizeof(double));
+}
+
+void carve_shared(Engine& E, char* p, int cap_members, int cap_tiles) {
+  E.shared = p;
+  E.cap_members = cap_members;
+  E.cap_tiles = cap_tiles;
+  E.d_descs = (lbk::LatticeDesc*)p;
+  p += align_up((size_t)cap_members * sizeof(lbk::LatticeDesc));
+  E.d_tile_lattice = (int*)p;
+  p += align_up((size_t)cap_tiles * sizeof(int));
+  E.red_out = (double*)p;
+}
+
+// Build a member record for parameters p over the device region `region`.
+Member make_member(const lb_params* p, char* region, bool owns, int64_t tag) {
+  Member mm;
+  mm.p = *p;
+  mm.p.device_buffer = nullptr;
+  mm.p.device_bytes = 0;
+  mm.d.g = make_geometry(p, 0);
+  mm.d.c = make_coefs(p);
+  mm.pop_bytes = align_up((size_t)mm.d.g.row_elems * (size_t)mm.d.g.ny * elem_size(p));
+  mm.wall_bytes = align_up(12ull * (size_t)p->nx * elem_size(p));
+  mm.max_tiles = max_tiles_of(p);
+  mm.region_bytes = member_region_bytes(p);
+  mm.region = region;
+  mm.owns_region = owns;
+  mm.tag = tag;
+  char* q = region;
+  mm.d.buf[0] = q;
+  mm.d.buf[1] = q + mm.pop_bytes;
+  q += 2 * mm.pop_bytes;
+  mm.d.wall[0] = q;
+  mm.d.wall[1] = q + mm.wall_bytes;
+  q += 2 * mm.wall_bytes;
+  mm.d.wave_red = (double*)q;
+  q += align_up((size_t)mm.max_tiles * lbk::kNRed * sizeof(double));
+  mm.d.wave_wall = (double*)q;
+  q += align_up((size_t)mm.max_tiles * 2 * sizeof(double));
+  mm.d.flag = (int*)q;
+  mm.d.phase = 0;
+  return mm;
+}
+
+int upload_descs(Engine& E) {
+  if (E.m.empty()) return LB_OK;
+  std::vector<lbk::LatticeDesc> h;
+  for (auto& mm : E.m) h.push_back(mm.d);
+  HIPCK(E, hipMemcpyAsync(E.d_descs, h.data(), h.size() * sizeof(lbk::LatticeDesc),
+                          hipMemcpyHostToDevice, E.stream));
+  // the host vector dies at return: make the copy complete first
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  return LB_OK;
+}
+
+void drop_graphs(Engine& E) {
+  for (auto*& gexec : E.graph) {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    gexec = nullptr;
+  }
+}
+
+// Grow the shared region of a dynamic engine to hold `members` lattices
+// and `tiles` tiles.
+int reserve_shared(Engine& E, int members, int tiles) {
+  if (members <= E.cap_members && tiles <= E.cap_tiles) return LB_OK;
+  if (!E.owns_shared) return E.fail(LB_E_NOMEM, "engine capacity exhausted");
+  const int cm = std::max(members, 2 * E.cap_members), ct = std::max(tiles, 2 * E.cap_tiles);
+  void* b = nullptr;
+  if (hipMalloc(&b, shared_bytes(cm, ct)) != hipSuccess) {
+    (void)hipGetLastError();
+    return E.fail(LB_E_NOMEM, "hipMalloc of the engine tables failed");
+  }
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  if (E.shared) {
+    (void)hipFree(E.shared);
+    E.bytes -= shared_bytes(E.cap_members, E.cap_tiles);
+  }
+  carve_shared(E, (char*)b, cm, ct);
+  E.bytes += shared_bytes(cm, ct);
+  return LB_OK;
+}
+
+// Assign tile bases from the members' geometries and rebuild the tile map.
+int retile(Engine& E) {
+  int base = 0;
+  std::vector<int> map;
+  for (int i = 0; i < (int)E.m.size(); ++i) {
+    E.m[i].d.tile_base = base;
+    base += E.m[i].d.g.ntiles;
+    map.insert(map.end(), E.m[i].d.g.ntiles, i);
+  }
+  const int rc = reserve_shared(E, (int)E.m.size(), base);
+  if (rc != LB_OK) return rc;
+  E.ntiles = base;
+  if (E.m.size() > 1) {
+    HIPCK(E, hipMemcpyAsync(E.d_tile_lattice, map.data(), map.size() * sizeof(int),
+                            hipMemcpyHostToDevice, E.stream));
+    HIPCK(E, hipStreamSynchronize(E.stream));
+  }
+  drop_graphs(E);
+  return upload_descs(E);
+}
+
+void choose_default_variant(Engine& E) {
+  // Defaults: prefetch for FP32 (registers allow it), streaming stores when
+  // the population buffers exceed the 256 MB Infinity Cache.
+  size_t total_pop = 0;
+  for (auto& mm : E.m) total_pop += 2 * mm.pop_bytes;
+  E.variant.prefetch = E.fp64 ? 0 : 1;
+  E.variant.stream_stores = total_pop > kInfinityCacheBytes ? 1 : 0;
+  if (const char* e = std::getenv("LBSOFT_PREFETCH")) E.variant.prefetch = std::atoi(e) ? 1 : 0;
+  if (const char* e = std::getenv("LBSOFT_STREAM_STORES"))
+    E.variant.stream_stores = std::atoi(e) ? 1 : 0;
+}
+
+lbk::LaunchArgs launch_args(const Engine& E, int parity) {
+  lbk::LaunchArgs a{};
+  a.descs = E.d_descs;
+  a.tile_lattice = E.m.size() > 1 ? E.d_tile_lattice : nullptr;
+  a.ntiles = E.ntiles;
+  a.tiles_per_xcd = (E.ntiles + 7) / 8;
+  a.parity = parity;
+  a.accumulate_wall = E.walls ? 1 : 0;
+  return a;
+}
+
+// Launch args for one member alone (observe / fields).
+lbk::LaunchArgs member_args(const Engine& E, int i) {
+  lbk::LaunchArgs a{};
+  a.descs = E.d_descs + i;
+  a.tile_lattice = nullptr;
+  a.ntiles = E.m[i].d.g.ntiles;
+  a.tiles_per_xcd = (a.ntiles + 7) / 8;
+  a.parity = (int)(E.step & 1);
+  return a;
+}
+
+int read_flags(Engine& E, std::vector<int>* out) {
+  std::vector<int> f(E.m.size(), 0);
+  for (size_t i = 0; i < E.m.size(); ++i)
+    HIPCK(E, hipMemcpyAsync(&f[i], E.m[i].d.flag, sizeof(int), hipMemcpyDeviceToHost, E.stream));
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  bool bad = false;
+  for (int v : f) bad |= (v & 1) != 0;
+  if (out) *out = f;
+  if (bad) return E.fail(LB_E_UNSTABLE, "non-finite or non-positive density on the device");
+  return LB_OK;
+}
+
+// Member i's state is set at engine step E.step: it starts in buf[0].
+void begin_member(Engine& E, int i, int64_t member_t) {
+  Member& mm = E.m[i];
+  mm.d.phase = (int)(E.step & 1);
+  mm.t_base = member_t;
+  mm.e_base = E.step;
+  mm.avg_start = E.step;
+  mm.initialized = true;
+}
+
+int zero_member_slots(Engine& E, int i) {
+  const Member& mm = E.m[i];
+  HIPCK(E, hipMemsetAsync(mm.d.wave_wall, 0, (size_t)mm.max_tiles * 2 * sizeof(double), E.stream));
+  HIPCK(E, hipMemsetAsync(mm.d.flag, 0, sizeof(int), E.stream));
+  return LB_OK;
+}
+
+void set_rho_ref(Engine& E, int i, const double* ra, const double* rb, size_t n) {
+  Member& mm = E.m[i];
+  if (E.fp64) return;
+  const double* r[2] = {ra, rb};
+  for (int s = 0; s < 2; ++s) {
+    if (mm.p.rho_ref[s] > 0) {
+      mm.d.c.rho_ref[s] = mm.p.rho_ref[s];
+      continue;
+    }
+    double acc = 0;
+    for (size_t k = 0; k < n; ++k) acc += r[s][k];
+    mm.d.c.rho_ref[s] = acc / (double)n;
+  }
+  round_coefs(mm.d.c);
+}
+
+int init_from_device_rho(Engine& E, int i, const double* d_rho, const double* d_u) {
+  Member& mm = E.m[i];
+  begin_member(E, i, 0);
+  int rc = upload_descs(E);
+  if (rc != LB_OK) return rc;
+  HIPCK(E, lbk::launch_init(mm.d.g, mm.d.c, E.fp64, E.walls, d_rho, d_u, mm.d.buf[0], mm.d.wall[0],
+                            E.stream));
+  rc = zero_member_slots(E, i);
+  if (rc != LB_OK) return rc;
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  return LB_OK;
+}
+
+// Capture two consecutive steps starting at the given parity into a graph.
+// Capture runs on a private non-blocking stream (the caller's stream may be
+// the null stream, which cannot be captured); replays go to the caller's
+// stream.  The graph holds the two kernel nodes only.
+int capture_pair(Engine& E, int parity) {
+  if (!E.capture_stream) HIPCK(E, hipStreamCreateWithFlags(&E.capture_stream, hipStreamNonBlocking));
+  HIPCK(E, hipStreamBeginCapture(E.capture_stream, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < 2; ++k) {
+    const hipError_t le = lbk::launch_step(launch_args(E, (parity + k) & 1), E.fp64, E.walls,
+                                           E.variant, E.capture_stream);
+    if (le != hipSuccess) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(E.capture_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      return E.fail(LB_E_DEVICE, std::string("capture: ") + hipGetErrorString(le));
+    }
+  }
+  hipGraph_t g = nullptr;
+  HIPCK(E, hipStreamEndCapture(E.capture_stream, &g));
+  const hipError_t ie = hipGraphInstantiate(&E.graph[parity], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    E.graph[parity] = nullptr;
+    return E.fail(LB_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  }
+  return LB_OK;
+}
+
+void fill_obs(const Engine& E, int i, const double* h, int flag, lb_obs* out) {
+  const Member& mm = E.m[i];
+  std::memset(out, 0, sizeof(*out));
+  out->step = member_time(E, i);
+  out->mass[0] = h[0];
+  out->mass[1] = h[1];
+  out->mom[0] = h[2];
+  out->mom[1] = h[3];
+  out->mom_phys[0] = h[4];
+  out->mom_phys[1] = h[5];
+  out->pxy_kin = h[6];
+  out->avg_count = E.step - mm.avg_start;
+  if (out->avg_count > 0 && E.walls) {
+    out->wall_stress[0] = h[lbk::kNRed + 0] / (double)out->avg_count / (double)mm.d.g.nx;
+    out->wall_stress[1] = h[lbk::kNRed + 1] / (double)out->avg_count / (double)mm.d.g.nx;
+  }
+  out->flags = flag;
+}
+
+}  // namespace
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  if (prev != dev) (void)hipSetDevice(dev);
+}
+DeviceGuard::~DeviceGuard() {
+  int cur = -1;
+  if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+}
+
+int validate(const lb_params* p, std::string* why) {
+  auto bad = [&](const char* msg) {
+    if (why) *why = msg;
+    return LB_E_INVAL;
+  };
+  if (!p) return bad("params is NULL");
+  if (p->nx < 5 || p->ny < 5) return bad("nx and ny must be >= 5");
+  if ((long long)p->nx * p->ny > (1LL << 30)) return bad("lattice larger than 2^30 sites");
+  if (p->boundary != LB_PERIODIC && p->boundary != LB_COUETTE_Y) return bad("unknown boundary");
+  if (p->precision != LB_FP64 && p->precision != LB_FP32_DEV) return bad("unknown precision");
+  for (int s = 0; s < 2; ++s) {
+    if (!is_finite(p->tau[s]) || !(p->tau[s] > 0.5)) return bad("tau must be > 1/2");
+    if (!is_finite(p->G_a[s]) || !is_finite(p->G_r[s])) return bad("couplings must be finite");
+    if (!is_finite(p->rho_ref[s])) return bad("rho_ref must be finite");
+  }
+  if (!is_finite(p->rho0) || !(p->rho0 > 0)) return bad("rho0 must be > 0");
+  if (!is_finite(p->G_AB)) return bad("G_AB must be finite");
+  if (!is_finite(p->u_wall)) return bad("u_wall must be finite");
+  return LB_OK;
+}
+
+size_t member_region_bytes(const lb_params* p) {
+  const lbk::Geometry g = make_geometry(p, 0);
+  const int mt = max_tiles_of(p);
+  const size_t pop = align_up((size_t)g.row_elems * (size_t)g.ny * elem_size(p));
+  const size_t wall = align_up(12ull * (size_t)p->nx * elem_size(p));
+  return 2 * pop + 2 * wall + align_up((size_t)mt * lbk::kNRed * sizeof(double)) +
+         align_up((size_t)mt * 2 * sizeof(double)) + kAlign;
+}
+
+size_t engine_static_bytes(const lb_params* ps, int n) {
+  int tiles = 0;
+  size_t regions = 0;
+  for (int i = 0; i < n; ++i) {
+    tiles += max_tiles_of(&ps[i]);
+    regions += member_region_bytes(&ps[i]);
+  }
+  return shared_bytes(n, tiles) + regions;
+}
+
+int engine_create_static(Engine& E, const lb_params* ps, int n, void* buffer, size_t buffer_bytes,
+                         hipStream_t stream) {
+  E.fp64 = ps[0].precision == LB_FP64;
+  E.walls = ps[0].boundary == LB_COUETTE_Y;
+  E.stream = stream;
+  if (hipGetDevice(&E.device) != hipSuccess) return E.fail(LB_E_DEVICE, "no HIP device");
+  const size_t total = engine_static_bytes(ps, n);
+  if (buffer) {
+    if (buffer_bytes < total || ((uintptr_t)buffer % kAlign) != 0)
+      return E.fail(LB_E_NOMEM, "device_buffer too small or not 256-byte aligned");
+    E.block = (char*)buffer;
+    E.owns_block = false;
+  } else {
+    void* b = nullptr;
+    if (hipMalloc(&b, total) != hipSuccess) {
+      (void)hipGetLastError();
+      return E.fail(LB_E_NOMEM, "hipMalloc of the workspace failed");
+    }
+    E.block = (char*)b;
+    E.owns_block = true;
+  }
+  E.bytes = total;
+  int tiles = 0;
+  for (int i = 0; i < n; ++i) tiles += max_tiles_of(&ps[i]);
+  carve_shared(E, E.block, n, tiles);
+  E.owns_shared = false;
+  char* q = E.block + shared_bytes(n, tiles);
+  for (int i = 0; i < n; ++i) {
+    E.m.push_back(make_member(&ps[i], q, false, i));
+    q += E.m.back().region_bytes;
+  }
+  choose_default_variant(E);
+  HIPCK(E, hipMemsetAsync(E.block, 0, total, E.stream));
+  const int rc = retile(E);
+  if (rc != LB_OK) return rc;
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  return LB_OK;
+}
+
+int engine_create_dynamic(Engine& E, bool fp64, bool walls, hipStream_t stream) {
+  E.fp64 = fp64;
+  E.walls = walls;
+  E.stream = stream;
+  E.owns_shared = true;
+  if (hipGetDevice(&E.device) != hipSuccess) return E.fail(LB_E_DEVICE, "no HIP device");
+  E.variant.prefetch = fp64 ? 0 : 1;
+  E.variant.stream_stores = 0;
+  return reserve_shared(E, 16, 4096);
+}
+
+int engine_add(Engine& E, const lb_params* p, int64_t tag, int* index) {
+  std::string why;
+  if (validate(p, &why) != LB_OK) return E.fail(LB_E_INVAL, why);
+  if ((p->precision == LB_FP64) != E.fp64 || (p->boundary == LB_COUETTE_Y) != E.walls)
+    return E.fail(LB_E_INVAL, "lattice precision / boundary differ from the engine's");
+  DeviceGuard dg(E.device);
+  const size_t rb = member_region_bytes(p);
+  void* r = nullptr;
+  if (hipMalloc(&r, rb) != hipSuccess) {
+    (void)hipGetLastError();
+    return E.fail(LB_E_NOMEM, "hipMalloc of a lattice failed");
+  }
+  HIPCK(E, hipMemsetAsync(r, 0, rb, E.stream));
+  E.m.push_back(make_member(p, (char*)r, true, tag));
+  E.bytes += rb;
+  const int rc = retile(E);
+  if (rc != LB_OK) {
+    (void)hipStreamSynchronize(E.stream);
+    (void)hipFree(r);
+    E.bytes -= rb;
+    E.m.pop_back();
+    return rc;
+  }
+  if (index) *index = (int)E.m.size() - 1;
+  return LB_OK;
+}
+
+int engine_remove(Engine& E, int index) {
+  if (index < 0 || index >= (int)E.m.size()) return E.fail(LB_E_INVAL, "lattice index out of range");
+  DeviceGuard dg(E.device);
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  if (E.m[index].owns_region) {
+    (void)hipFree(E.m[index].region);
+    E.bytes -= E.m[index].region_bytes;
+  }
+  E.m.erase(E.m.begin() + index);
+  return retile(E);
+}
+
+void engine_destroy(Engine& E) {
+  DeviceGuard dg(E.device);
+  (void)hipStreamSynchronize(E.stream);
+  drop_graphs(E);
+  if (E.capture_stream) (void)hipStreamDestroy(E.capture_stream);
+  E.capture_stream = nullptr;
+  for (auto& mm : E.m)
+    if (mm.owns_region && mm.region) (void)hipFree(mm.region);
+  E.m.clear();
+  if (E.owns_shared && E.shared) (void)hipFree(E.shared);
+  if (E.owns_block && E.block) (void)hipFree(E.block);
+  E.shared = nullptr;
+  E.block = nullptr;
+}
+
+int engine_init(Engine& E, int i, const double* rho_a, const double* rho_b, const double* ux,
+                const double* uy) {
+  if (i < 0 || i >= (int)E.m.size()) return E.fail(LB_E_INVAL, "lattice index out of range");
+  if (!rho_a || !rho_b) return E.fail(LB_E_INVAL, "rho_a and rho_b are required");
+  if ((ux == nullptr) != (uy == nullptr)) return E.fail(LB_E_INVAL, "give both ux and uy or neither");
+  const Member& mm = E.m[i];
+  const size_t n = (size_t)mm.d.g.nx * mm.d.g.ny;
+  for (size_t k = 0; k < n; ++k) {
+    if (!is_finite(rho_a[k]) || !(rho_a[k] > 0) || !is_finite(rho_b[k]) || !(rho_b[k] > 0))
+      return E.fail(LB_E_INVAL, "densities must be finite and > 0");
+    if (ux && (!is_finite(ux[k]) || !is_finite(uy[k])))
+      return E.fail(LB_E_INVAL, "velocities must be finite");
+  }
+  DeviceGuard dg(E.device);
+  set_rho_ref(E, i, rho_a, rho_b, n);
+  DevTmp t;
+  const size_t nb = n * sizeof(double);
+  HIPCK(E, hipMalloc(&t.p, (ux ? 4 : 2) * nb));
+  double* d = (double*)t.p;
+  HIPCK(E, hipMemcpyAsync(d, rho_a, nb, hipMemcpyHostToDevice, E.stream));
+  HIPCK(E, hipMemcpyAsync(d + n, rho_b, nb, hipMemcpyHostToDevice, E.stream));
+  if (ux) {
+    HIPCK(E, hipMemcpyAsync(d + 2 * n, ux, nb, hipMemcpyHostToDevice, E.stream));
+    HIPCK(E, hipMemcpyAsync(d + 3 * n, uy, nb, hipMemcpyHostToDevice, E.stream));
+  }
+  return init_from_device_rho(E, i, d, ux ? d + 2 * n : nullptr);
+}
+
+int engine_init_noise(Engine& E, int i, uint64_t seed, double mean_a, double mean_b, double amp) {
+  if (i < 0 || i >= (int)E.m.size()) return E.fail(LB_E_INVAL, "lattice index out of range");
+  if (!is_finite(mean_a) || !is_finite(mean_b) || !is_finite(amp) ||
+      !(std::fabs(amp) < std::min(mean_a, mean_b)))
+    return E.fail(LB_E_INVAL, "need |amp| < min(mean_a, mean_b) and finite values");
+  DeviceGuard dg(E.device);
+  Member& mm = E.m[i];
+  if (!E.fp64) {
+    mm.d.c.rho_ref[0] = mm.p.rho_ref[0] > 0 ? mm.p.rho_ref[0] : mean_a;
+    mm.d.c.rho_ref[1] = mm.p.rho_ref[1] > 0 ? mm.p.rho_ref[1] : mean_b;
+    round_coefs(mm.d.c);
+  }
+  const size_t n = (size_t)mm.d.g.nx * mm.d.g.ny;
+  DevTmp t;
+  HIPCK(E, hipMalloc(&t.p, 2 * n * sizeof(double)));
+  HIPCK(E, lbk::launch_noise(mm.d.g.nx, mm.d.g.ny, seed, mean_a, mean_b, amp, (double*)t.p, E.stream));
+  return init_from_device_rho(E, i, (const double*)t.p, nullptr);
+}
+
+int engine_step(Engine& E, int64_t n) {
+  if (n < 0) return E.fail(LB_E_INVAL, "n must be >= 0");
+  if (E.m.empty()) return n == 0 ? LB_OK : E.fail(LB_E_STATE, "no lattices to step");
+  for (auto& mm : E.m)
+    if (!mm.initialized) return E.fail(LB_E_STATE, "step before every lattice is initialized");
+  DeviceGuard dg(E.device);
+  int64_t k = 0;
+  if (E.use_graph && n >= 2) {
+    const int par = (int)(E.step & 1);
+    if (!E.graph[par]) {
+      const int rc = capture_pair(E, par);
+      if (rc != LB_OK) return rc;
+    }
+    for (; k + 2 <= n; k += 2) {
+      HIPCK(E, hipGraphLaunch(E.graph[par], E.stream));
+      E.step += 2;
+    }
+  }
+  for (; k < n; ++k) {
+    HIPCK(E, lbk::launch_step(launch_args(E, (int)(E.step & 1)), E.fp64, E.walls, E.variant, E.stream));
+    ++E.step;
+  }
+  return LB_OK;
+}
+
+int engine_observables(Engine& E, lb_obs* out /*[n]*/) {
+  for (auto& mm : E.m)
+    if (!mm.initialized) return E.fail(LB_E_STATE, "observables before every lattice is initialized");
+  if (E.m.empty()) return LB_OK;
+  DeviceGuard dg(E.device);
+  const int n = (int)E.m.size();
+  HIPCK(E, lbk::launch_observe(launch_args(E, (int)(E.step & 1)), E.fp64, E.walls, E.stream));
+  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs, n, 0, E.red_out, 16, E.stream));
+  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs, n, 1, E.red_out + lbk::kNRed, 16, E.stream));
+  std::vector<double> h((size_t)n * 16);
+  HIPCK(E, hipMemcpyAsync(h.data(), E.red_out, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          E.stream));
+  std::vector<int> flags;
+  const int rc = read_flags(E, &flags);
+  if (flags.size() != (size_t)n) return rc;
+  for (int i = 0; i < n; ++i) fill_obs(E, i, h.data() + (size_t)i * 16, flags[i], out + i);
+  return rc;
+}
+
+int engine_member_observables(Engine& E, int i, lb_obs* out) {
+  if (i < 0 || i >= (int)E.m.size()) return E.fail(LB_E_INVAL, "lattice index out of range");
+  if (!E.m[i].initialized) return E.fail(LB_E_STATE, "observables before lb_init");
+  DeviceGuard dg(E.device);
+  HIPCK(E, lbk::launch_observe(member_args(E, i), E.fp64, E.walls, E.stream));
+  double* row = E.red_out + (size_t)i * 16;
+  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs + i, 1, 0, row, 16, E.stream));
+  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs + i, 1, 1, row + lbk::kNRed, 16, E.stream));
+  double h[16];
+  int flag = 0;
+  HIPCK(E, hipMemcpyAsync(h, row, sizeof(h), hipMemcpyDeviceToHost, E.stream));
+  HIPCK(E, hipMemcpyAsync(&flag, E.m[i].d.flag, sizeof(int), hipMemcpyDeviceToHost, E.stream));
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  fill_obs(E, i, h, flag, out);
+  if (flag & 1) return E.fail(LB_E_UNSTABLE, "non-finite or non-positive density on the device");
+  return LB_OK;
+}
+
+int engine_fields(Engine& E, int i, double* rho_a, double* rho_b, double* u, double* u_phys) {
+  if (i < 0 || i >= (int)E.m.size()) return E.fail(LB_E_INVAL, "lattice index out of range");
+  if (!E.m[i].initialized) return E.fail(LB_E_STATE, "fields before lb_init");
+  DeviceGuard dg(E.device);
+  const size_t n = (size_t)E.m[i].d.g.nx * E.m[i].d.g.ny, nb = n * sizeof(double);
+  DevTmp t;
+  HIPCK(E, hipMalloc(&t.p, 6 * nb));
+  double* d = (double*)t.p;
+  lbk::LaunchArgs a = member_args(E, i);
+  a.fields = d;
+  HIPCK(E, lbk::launch_observe(a, E.fp64, E.walls, E.stream));
+  if (rho_a) HIPCK(E, hipMemcpyAsync(rho_a, d, nb, hipMemcpyDeviceToHost, E.stream));
+  if (rho_b) HIPCK(E, hipMemcpyAsync(rho_b, d + n, nb, hipMemcpyDeviceToHost, E.stream));
+  if (u) HIPCK(E, hipMemcpyAsync(u, d + 2 * n, 2 * nb, hipMemcpyDeviceToHost, E.stream));
+  if (u_phys) HIPCK(E, hipMemcpyAsync(u_phys, d + 4 * n, 2 * nb, hipMemcpyDeviceToHost, E.stream));
+  return read_flags(E, nullptr);
+}
+
+int engine_pops(Engine& E, int i, double* f) {
+  if (i < 0 || i >= (int)E.m.size() || !f) return E.fail(LB_E_INVAL, "bad lattice index or NULL f");
+  if (!E.m[i].initialized) return E.fail(LB_E_STATE, "populations before lb_init");
+  DeviceGuard dg(E.device);
+  const size_t n = (size_t)E.m[i].d.g.nx * E.m[i].d.g.ny, nb = 18 * n * sizeof(double);
+  DevTmp t;
+  HIPCK(E, hipMalloc(&t.p, nb));
+  lbk::LaunchArgs a = member_args(E, i);
+  a.pops = (double*)t.p;
+  HIPCK(E, lbk::launch_observe(a, E.fp64, E.walls, E.stream));
+  HIPCK(E, hipMemcpyAsync(f, t.p, nb, hipMemcpyDeviceToHost, E.stream));
+  return read_flags(E, nullptr);
+}
+
+int engine_set_pops(Engine& E, int i, const double* f, int64_t member_t) {
+  if (i < 0 || i >= (int)E.m.size() || !f) return E.fail(LB_E_INVAL, "bad lattice index or NULL f");
+  if (member_t < 0) return E.fail(LB_E_INVAL, "step must be >= 0");
+  Member& mm = E.m[i];
+  const size_t n = (size_t)mm.d.g.nx * mm.d.g.ny;
+  for (size_t k = 0; k < 18 * n; ++k)
+    if (!is_finite(f[k])) return E.fail(LB_E_INVAL, "populations must be finite");
+  DeviceGuard dg(E.device);
+  if (!E.fp64 && !mm.initialized) {
+    // reference densities from these populations when none were given
+    std::vector<double> ra(n, 0.0), rb(n, 0.0);
+    for (int q = 0; q < 9; ++q)
+      for (size_t k = 0; k < n; ++k) {
+        ra[k] += f[(size_t)q * n + k];
+        rb[k] += f[(size_t)(9 + q) * n + k];
+      }
+    set_rho_ref(E, i, ra.data(), rb.data(), n);
+  }
+  DevTmp t;
+  HIPCK(E, hipMalloc(&t.p, 18 * n * sizeof(double)));
+  HIPCK(E, hipMemcpyAsync(t.p, f, 18 * n * sizeof(double), hipMemcpyHostToDevice, E.stream));
+  begin_member(E, i, member_t);
+  int rc = upload_descs(E);
+  if (rc != LB_OK) return rc;
+  HIPCK(E, lbk::launch_set_pops(mm.d.g, mm.d.c, E.fp64, E.walls, (const double*)t.p, mm.d.buf[0],
+                                mm.d.wall[0], E.stream));
+  rc = zero_member_slots(E, i);
+  if (rc != LB_OK) return rc;
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  return LB_OK;
+}
+
+int engine_reset_averages(Engine& E) {
+  DeviceGuard dg(E.device);
+  for (auto& mm : E.m) {
+    HIPCK(E, hipMemsetAsync(mm.d.wave_wall, 0, (size_t)mm.max_tiles * 2 * sizeof(double), E.stream));
+    mm.avg_start = E.step;
+  }
+  return LB_OK;
+}
+
+int engine_sync(Engine& E) {
+  DeviceGuard dg(E.device);
+  return read_flags(E, nullptr);
+}
+
+int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32_t use_graph) {
+  if (prefetch >= 0) E.variant.prefetch = prefetch ? 1 : 0;
+  if (stream_stores >= 0) E.variant.stream_stores = stream_stores ? 1 : 0;
+  if (use_graph >= 0) E.use_graph = use_graph != 0;
+  drop_graphs(E);
+  return LB_OK;
+}
+
+int engine_regrid(Engine& E, int seg_h) {
+  DeviceGuard dg(E.device);
+  for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, seg_h);
+  const int rc = retile(E);
+  if (rc != LB_OK) return rc;
+  return engine_reset_averages(E);
+}
+
+void engine_info(const Engine& E, lb_launch_info* out) {
+  std::memset(out, 0, sizeof(*out));
+  out->ntiles = E.ntiles;
+  out->grid_blocks = 8 * ((E.ntiles + 7) / 8);
+  out->block_threads = lbk::kWave;
+  out->workspace_bytes = E.bytes;
+  size_t pb = 0;
+  for (auto& mm : E.m) pb += mm.pop_bytes;
+  out->population_bytes = pb;
+  if (!E.m.empty()) {
+    const auto& g = E.m[0].d.g;
+    out->nstrips = g.nstrips;
+    out->nsegs = g.nsegs;
+    out->pitch = g.pitch;
+    out->seg_h = g.seg_h;
+  }
+  out->prefetch = E.variant.prefetch;
+  out->stream_stores = E.variant.stream_stores;
+  out->use_graph = E.use_graph ? 1 : 0;
+}
+
+int64_t member_time(const Engine& E, int i) {
+  const Member& mm = E.m[i];
+  return mm.t_base + (E.step - mm.e_base);
+}
+
+int member_index(const Engine& E, int64_t tag) {
+  for (int i = 0; i < (int)E.m.size(); ++i)
+    if (E.m[i].tag == tag) return i;
+  return -1;
+}
+
+}  // namespace lbe

@@ -62,6 +62,8 @@ struct LatticeDesc {
   void* buf[2];   // population buffers (pull layout)
   void* wall[2];  // wall-link buffers
   int* flag;      // bit 0 set when a density is non-finite or <= 0
+  double* wave_red;   // observe: kNRed values per tile of this lattice
+  double* wave_wall;  // step: wall-momentum accumulators (bottom, top) per tile
   int tile_base;  // first tile of this lattice in its launch's tile list
   int phase;      // with launch step parity p the lattice reads buf[p ^ phase]
 };
@@ -74,11 +76,9 @@ struct LaunchArgs {
   int ntiles;                // tiles in the launch
   int tiles_per_xcd;         // ceil(ntiles / 8): tiles are handed out XCD-major
   int parity;                // launch step parity
-  double* wave_red;          // observe: kNRed values per tile
-  double* wave_wall;         // step: 2 accumulators (bottom, top wall) per tile
   double* fields;            // observe, single lattice: [6][ny][nx] or null
   double* pops;              // observe, single lattice: [2][9][ny][nx] or null
-  int accumulate_wall;       // step: add wall momentum to wave_wall
+  int accumulate_wall;       // step: add wall momentum to the lattices' wave_wall
 };
 
 // Code variants of the step kernel (tuning choices, same arithmetic).
@@ -91,11 +91,11 @@ struct StepVariant {
 hipError_t launch_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
                        hipStream_t st);
 hipError_t launch_observe(const LaunchArgs& a, bool fp64, bool walls, hipStream_t st);
-// Fixed-order per-lattice sums: for lattice m of descs[0..n), the `width`
-// per-tile values of its tiles [tile_base, tile_base + ntiles) of `in` are
-// summed into out[m * out_stride + 0 .. width).
-hipError_t launch_reduce_lattices(const LatticeDesc* descs, int n, const double* in, int width,
-                                  double* out, int out_stride, hipStream_t st);
+// Fixed-order per-lattice sums of the per-tile slots of each lattice of
+// descs[0..n): its kNRed observe values (which = 0) or its 2 wall
+// accumulators (which = 1), into out[m * out_stride + 0 ..).
+hipError_t launch_reduce_lattices(const LatticeDesc* descs, int n, int which, double* out,
+                                  int out_stride, hipStream_t st);
 // Write the t = 0 state: src buffer in pull layout plus the wall links, from
 // FP64 densities / velocities on the device (u may be null).
 hipError_t launch_init(const Geometry& g, const Coefs& c, bool fp64, bool walls,

@@ -513,7 +513,7 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
       double v = acc[m];
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-      if (lane == 0) a.wave_red[(long long)tile * kNRed + m] = v;
+      if (lane == 0) D->wave_red[(long long)local * kNRed + m] = v;
     }
   } else if (WALLS && a.accumulate_wall && (y0 == 0 || y1 == ny)) {
 #pragma unroll
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
       double v = wacc[m];
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-      if (lane == 0) a.wave_wall[(long long)tile * 2 + m] += v;
+      if (lane == 0) D->wave_wall[(long long)local * 2 + m] += v;
     }
   }
 }
@@ -531,14 +531,16 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
 // binary tree.  The result depends only on the lattice's own tiles, so it is
 // the same bit for bit whether the lattice ran alone or in a batch.
 __global__ __launch_bounds__(256) void k_reduce_lattices(const LatticeDesc* __restrict__ descs,
-                                                         const double* __restrict__ in, int width,
-                                                         double* __restrict__ out, int out_stride) {
+                                                         int which, double* __restrict__ out,
+                                                         int out_stride) {
   __shared__ double sh[256];
   const LatticeDesc* D = descs + blockIdx.x;
-  const int base = D->tile_base, ntiles = D->g.ntiles;
+  const int ntiles = D->g.ntiles;
+  const double* __restrict__ in = which ? D->wave_wall : D->wave_red;
+  const int width = which ? 2 : kNRed;
   for (int m = 0; m < width; ++m) {
     double v = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += 256) v += in[(long long)(base + t) * width + m];
+    for (int t = threadIdx.x; t < ntiles; t += 256) v += in[(long long)t * width + m];
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int h = 128; h >= 1; h >>= 1) {
@@ -681,10 +683,10 @@ hipError_t launch_observe(const LaunchArgs& a, bool fp64, bool walls, hipStream_
   return launch_march<kObserve, 0, false>(a, fp64, walls, st);
 }
 
-hipError_t launch_reduce_lattices(const LatticeDesc* descs, int n, const double* in, int width,
-                                  double* out, int out_stride, hipStream_t st) {
+hipError_t launch_reduce_lattices(const LatticeDesc* descs, int n, int which, double* out,
+                                  int out_stride, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_lattices, dim3(n), dim3(256), 0, st, descs, in, width, out, out_stride);
+  hipLaunchKernelGGL(k_reduce_lattices, dim3(n), dim3(256), 0, st, descs, which, out, out_stride);
   return hipGetLastError();
 }
 

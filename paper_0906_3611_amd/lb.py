@@ -368,3 +368,125 @@ class Batch(_Handle):
     def set_launch(self, prefetch=-1, stream_stores=-1, use_graph=-1):
         self._check(self._lib.lb_batch_set_launch(self._h, int(prefetch), int(stream_stores),
                                                   int(use_graph)), "lb_batch_set_launch")
+
+
+LB_JOB_QUEUED, LB_JOB_RUNNING, LB_JOB_DONE, LB_JOB_FAILED = 0, 1, 2, 3
+
+
+class lb_pool_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("running", ctypes.c_int64), ("done", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("resident_bytes", ctypes.c_size_t), ("budget_bytes", ctypes.c_size_t),
+                ("site_updates", ctypes.c_int64), ("ticks", ctypes.c_int64),
+                ("steps", ctypes.c_int64), ("clock", ctypes.c_double)]
+
+
+def _load_pool_symbols(L):
+    P = ctypes.POINTER
+    h, dp, i64, i32 = ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64, ctypes.c_int32
+    sig = {
+        "lb_pool_create": ([ctypes.c_size_t, h, P(h)], ctypes.c_int),
+        "lb_pool_destroy": ([h], None),
+        "lb_pool_last_error": ([h], ctypes.c_char_p),
+        "lb_pool_set_options": ([h, i32, i32], ctypes.c_int),
+        "lb_pool_job_bytes": ([P(lb_params)], ctypes.c_size_t),
+        "lb_pool_submit_noise": ([h, P(lb_params), ctypes.c_uint64, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_double, i64, P(i64)], ctypes.c_int),
+        "lb_pool_submit": ([h, P(lb_params), dp, dp, i64, P(i64)], ctypes.c_int),
+        "lb_pool_advance": ([h, i64], ctypes.c_int),
+        "lb_pool_job_state": ([h, i64, P(i32)], ctypes.c_int),
+        "lb_pool_job_result": ([h, i64, P(lb_obs), dp, dp, dp], ctypes.c_int),
+        "lb_pool_release": ([h, i64], ctypes.c_int),
+        "lb_pool_get_stats": ([h, P(lb_pool_stats)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+
+
+def job_bytes(**spec) -> int:
+    """Device footprint of one pool job with these parameters."""
+    L = load()
+    _load_pool_symbols(L)
+    sp = dict(spec)
+    nx, ny = sp.pop("nx"), sp.pop("ny")
+    return int(L.lb_pool_job_bytes(ctypes.byref(make_params(nx, ny, **sp))))
+
+
+class Pool(_Handle):
+    """Serving pool: jobs admitted under an HBM budget, advanced together,
+    retired with their results copied to the host (see include/lb.h)."""
+    _destroy = "lb_pool_destroy"
+    _last_error = "lb_pool_last_error"
+
+    def __init__(self, budget_bytes, stream=None, keep_fields=True, use_graph=True):
+        self._lib = load()
+        _load_pool_symbols(self._lib)
+        self._h = ctypes.c_void_p()
+        self._buf = None
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.shapes = {}
+        self._check(self._lib.lb_pool_create(int(budget_bytes), stream.cuda_stream,
+                                             ctypes.byref(self._h)), "lb_pool_create")
+        self._check(self._lib.lb_pool_set_options(self._h, int(keep_fields), int(use_graph)),
+                    "lb_pool_set_options")
+
+    def submit_noise(self, steps, seed, mean_a, mean_b, amp, **spec) -> int:
+        sp = dict(spec)
+        nx, ny = sp.pop("nx"), sp.pop("ny")
+        p = make_params(nx, ny, **sp)
+        jid = ctypes.c_int64()
+        self._check(self._lib.lb_pool_submit_noise(self._h, ctypes.byref(p), int(seed), float(mean_a),
+                                                   float(mean_b), float(amp), int(steps),
+                                                   ctypes.byref(jid)), "lb_pool_submit_noise")
+        self.shapes[jid.value] = (int(ny), int(nx))
+        return jid.value
+
+    def submit(self, steps, rho_a, rho_b, **spec) -> int:
+        sp = dict(spec)
+        nx, ny = sp.pop("nx"), sp.pop("ny")
+        p = make_params(nx, ny, **sp)
+        ra, rb = _f64(rho_a, (ny, nx)), _f64(rho_b, (ny, nx))
+        jid = ctypes.c_int64()
+        self._check(self._lib.lb_pool_submit(self._h, ctypes.byref(p), _dptr(ra), _dptr(rb),
+                                             int(steps), ctypes.byref(jid)), "lb_pool_submit")
+        self.shapes[jid.value] = (int(ny), int(nx))
+        return jid.value
+
+    def advance(self, n):
+        self._check(self._lib.lb_pool_advance(self._h, int(n)), "lb_pool_advance")
+
+    def state(self, jid) -> int:
+        s = ctypes.c_int32()
+        self._check(self._lib.lb_pool_job_state(self._h, int(jid), ctypes.byref(s)), "lb_pool_job_state")
+        return s.value
+
+    def times(self, jid):
+        t = np.zeros(3)
+        self._lib.lb_pool_job_result(self._h, int(jid), None, _dptr(None), _dptr(None), _dptr(t))
+        return t
+
+    def result(self, jid, fields=True) -> dict:
+        o = lb_obs()
+        t = np.zeros(3)
+        ny, nx = self.shapes[jid]
+        ra = np.empty((ny, nx)) if fields else None
+        rb = np.empty((ny, nx)) if fields else None
+        self._check(self._lib.lb_pool_job_result(self._h, int(jid), ctypes.byref(o), _dptr(ra),
+                                                 _dptr(rb), _dptr(t)), "lb_pool_job_result")
+        out = {"obs": _obs_dict(o), "times": t}
+        if fields:
+            out["rho"] = np.stack([ra, rb])
+        return out
+
+    def release(self, jid):
+        self._check(self._lib.lb_pool_release(self._h, int(jid)), "lb_pool_release")
+
+    def stats(self) -> dict:
+        s = lb_pool_stats()
+        self._check(self._lib.lb_pool_get_stats(self._h, ctypes.byref(s)), "lb_pool_get_stats")
+        return {k: getattr(s, k) for k, _ in lb_pool_stats._fields_}

@@ -1,0 +1,87 @@
+"""Serving pool: jobs admitted under an HBM budget and advanced together end
+exactly where the same job run alone ends (bit for bit), whatever else was
+resident; the budget is never exceeded."""
+import numpy as np
+import pytest
+import torch  # noqa: F401
+
+from paper_0906_3611_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405,
+            precision="fp32dev")
+
+
+def _lb():
+    from paper_0906_3611_amd import lb
+    return lb
+
+
+def _jobs():
+    out = []
+    for k, (nx, ny, steps, bnd) in enumerate(((64, 64, 40, "periodic"), (130, 70, 25, "couette"),
+                                                (96, 40, 60, "periodic"), (70, 33, 7, "couette"),
+                                                (200, 120, 33, "periodic"), (64, 64, 0, "periodic"))):
+        sp = dict(BASE, nx=nx, ny=ny, boundary=bnd, u_wall=0.01 if bnd == "couette" else 0.0)
+        out.append((sp, steps, 50 + k))
+    return out
+
+
+def _alone(sp, steps, seed):
+    lb = _lb()
+    kw = dict(sp)
+    nx, ny = kw.pop("nx"), kw.pop("ny")
+    lat = lb.Lattice(nx, ny, **kw)
+    ra, rb = inputs.noise_fields(nx, ny, seed, 0.5, 0.5, 0.05)
+    lat.init(ra, rb)
+    lat.step(steps)
+    return lat.fields()["rho"], lat.observables()
+
+
+@pytest.mark.parametrize("budget_frac", [1.0, 0.3])
+def test_pool_results_match_lone_runs(budget_frac):
+    lb = _lb()
+    jobs = _jobs()
+    total = sum(lb.job_bytes(**sp) for sp, _, _ in jobs)
+    biggest = max(lb.job_bytes(**sp) for sp, _, _ in jobs)
+    budget = max(int(total * budget_frac), biggest)
+    pool = lb.Pool(budget)
+    ids = []
+    for sp, steps, seed in jobs:
+        ra, rb = inputs.noise_fields(sp["nx"], sp["ny"], seed, 0.5, 0.5, 0.05)
+        ids.append(pool.submit(steps, ra, rb, **sp))
+    peak = 0
+    for _ in range(200):
+        pool.advance(9)
+        st = pool.stats()
+        peak = max(peak, st["resident_bytes"])
+        if st["done"] + st["failed"] == len(jobs):
+            break
+    st = pool.stats()
+    assert st["done"] == len(jobs) and st["failed"] == 0
+    assert peak <= budget
+    for jid, (sp, steps, seed) in zip(ids, jobs):
+        res = pool.result(jid)
+        rho, obs = _alone(sp, steps, seed)
+        assert res["obs"]["step"] == steps
+        assert np.array_equal(res["rho"], rho), jid
+        assert np.array_equal(res["obs"]["mass"], obs["mass"]), jid
+        t = res["times"]
+        assert t[0] <= t[1] <= t[2]
+    pool.close()
+
+
+def test_pool_rejects_oversized_job():
+    lb = _lb()
+    sp = dict(BASE, nx=256, ny=256)
+    pool = lb.Pool(lb.job_bytes(**sp) - 1)
+    with pytest.raises(lb.LBError) as ei:
+        pool.submit_noise(10, 1, 0.5, 0.5, 0.01, **sp)
+    assert ei.value.code == lb.LB_E_NOMEM
+    small = dict(BASE, nx=64, ny=64)
+    jid = pool.submit_noise(10, 1, 0.5, 0.5, 0.01, **small)
+    pool.advance(10)
+    assert pool.state(jid) == lb.LB_JOB_DONE
+    pool.release(jid)
+    pool.close()
