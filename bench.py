@@ -97,6 +97,261 @@ def cpu_baseline(nx, ny, rho_a, rho_b, budget_s=15.0):
             "sample": f"{nx}x{ny} disc emulsion, FP64, {n} steps after 1 untimed, {dt:.1f} s"}
 
 
+def _timed(stream, fn):
+    """GPU time (ms) of the work fn() enqueues on `stream`, by HIP events."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
+    """Planar Couette channel 4096 x 1024 (walls on y, periodic x) in FP32
+    storage: throughput over `steps` steps per wall speed, wall stress
+    averaged over the second half.  Then the reduced stress-vs-shear-rate
+    curve on a 512 x 128 channel (one batch of the three speeds, graph
+    replay), averaged over the second half of `curve_steps` steps."""
+    from paper_0906_3611_amd import inputs, lb
+    nx, ny = 4096, 1024
+    ra, rb = inputs.noise_fields(nx, ny, 3, 0.5, 0.5, 0.01)
+    runs = []
+    for U in speeds:
+        lat = lb.Lattice(nx, ny, precision="fp32dev", boundary="couette", u_wall=U, **PARAMS)
+        lat.init(ra, rb)
+        h = steps // 2
+        ms = _timed(lat.stream, lambda: lat.step(h))
+        lat.reset_averages()
+        ms += _timed(lat.stream, lambda: lat.step(steps - h))
+        o = lat.observables()
+        runs.append({"U": U, "value": nx * ny * steps / (ms * 1e-3) / 1e6,
+                     "ms_per_step": ms / steps,
+                     "wall_stress_bottom_top": list(o["wall_stress"]),
+                     "mass_rel_drift": [abs(o["mass"][s] / (0.5 * nx * ny) - 1.0) for s in (0, 1)]})
+        lat.close()
+        print(f"# couette {nx}x{ny} U={U}: {runs[-1]['value']:.0f} MLUPS", file=sys.stderr, flush=True)
+    cx, cy = 512, 128
+    specs = [dict(PARAMS, nx=cx, ny=cy, precision="fp32dev", boundary="couette", u_wall=U) for U in speeds]
+    b = lb.Batch(specs)
+    for i in range(len(speeds)):
+        b.init_noise(i, 3, 0.5, 0.5, 0.01)
+    b.set_launch(use_graph=1)
+    h = curve_steps // 2
+    ms = _timed(b.stream, lambda: b.step(h))
+    b.reset_averages()
+    ms += _timed(b.stream, lambda: b.step(curve_steps - h))
+    obs = b.observables()
+    eta0 = 1.0 * (PARAMS["tau"][0] - 0.5) / 3.0  # rho nu of the mixture at total density 1
+    curve = []
+    for U, o in zip(speeds, obs):
+        bottom, top = o["wall_stress"]
+        sigma = 0.5 * (bottom - top)
+        rate = 2.0 * U / cy
+        curve.append({"U": U, "shear_rate": rate, "stress": sigma,
+                      "apparent_viscosity_ratio": sigma / rate / eta0,
+                      "wall_stress_bottom_top": [bottom, top]})
+    b.close()
+    return {"workload": f"{nx}x{ny} Couette channel, walls at -/+U on y, noise 0.5+-0.01 seed 3, "
+                        f"fp32dev, {steps} steps per U (stress over the second half)",
+            "runs": runs,
+            "reduced_curve": {"workload": f"{cx}x{cy} channel (reduced), three speeds batched, "
+                                          f"{curve_steps} steps, stress averaged over the second half",
+                              "value": len(speeds) * cx * cy * curve_steps / (ms * 1e-3) / 1e6,
+                              "points": curve}}
+
+
+def bench_batch(n=256, steps=5000, seed=4, tune_steps=10):
+    """Ensemble of n independent square lattices (sides log-uniform in
+    [128, 1024], G^a in [-9.5, -8.5], disc fraction in [0.5, 0.8]) in FP32
+    storage: all of them advanced by one launch per step (autotuned common
+    tile height, graph replay) versus the same kernels one lattice at a time,
+    each lattice with its own autotuned launch shape and graph replay.  Every
+    lattice's density fields must agree bit for bit between the two."""
+    from concurrent.futures import ThreadPoolExecutor
+    import numpy as np
+    from paper_0906_3611_amd import inputs, lb
+    specs = inputs.ensemble_specs(n, seed)
+    ps = [dict(PARAMS, nx=s["L"], ny=s["L"], G_a=(s["G_a"], s["G_a"]), precision="fp32dev")
+          for s in specs]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        fields = list(ex.map(lambda s: lb.disc_fields(s["L"], s["L"], s["seed"], s["phi"]), specs))
+    t_gen = time.perf_counter() - t0
+    sites = sum(s["L"] ** 2 for s in specs)
+    b = lb.Batch(ps)
+    for i, (ra, rb) in enumerate(fields):
+        b.init(i, ra, rb)
+    b.set_launch(use_graph=1)
+    tuned = b.autotune(steps=tune_steps)
+    ms_b = _timed(b.stream, lambda: b.step(steps))
+    b.observables()  # raises on instability
+    batch_mlups = sites * steps / (ms_b * 1e-3) / 1e6
+    print(f"# batch {n} lattices ({sites} sites): {batch_mlups:.0f} MLUPS", file=sys.stderr, flush=True)
+    ms_seq, mismatched = 0.0, []
+    t0 = time.perf_counter()
+    for i, (sp, (ra, rb)) in enumerate(zip(ps, fields)):
+        kw = dict(sp)
+        nx, ny = kw.pop("nx"), kw.pop("ny")
+        lat = lb.Lattice(nx, ny, **kw)
+        lat.init(ra, rb)
+        lat.set_launch(use_graph=1)
+        lat.autotune(steps=tune_steps)
+        ms_seq += _timed(lat.stream, lambda: lat.step(steps))
+        if not np.array_equal(lat.fields()["rho"], b.fields(i)["rho"]):
+            mismatched.append(i)
+        lat.close()
+    wall_seq = time.perf_counter() - t0
+    b.close()
+    seq_mlups = sites * steps / (ms_seq * 1e-3) / 1e6
+    print(f"# one at a time: {seq_mlups:.0f} MLUPS", file=sys.stderr, flush=True)
+    return {"workload": f"{n} square lattices, sides log-uniform in [128, 1024] (seed {seed}), "
+                        f"G^a in [-9.5, -8.5], disc fraction in [0.5, 0.8], fp32dev, {steps} steps",
+            "sites": sites, "value": batch_mlups, "ms_per_step": ms_b / steps,
+            "batch_launch": {k: tuned[k] for k in ("seg_h", "ntiles", "prefetch", "stream_stores",
+                                                   "use_graph", "us_per_step")},
+            "one_at_a_time": {"value": seq_mlups, "gpu_ms": ms_seq, "wall_s": wall_seq},
+            "speedup": batch_mlups / seq_mlups,
+            "fields_bitwise_equal": not mismatched, "mismatched": mismatched[:8],
+            "host_disc_generation_s": t_gen}
+
+
+def _percentiles(x):
+    import numpy as np
+    x = np.asarray(x, dtype=float)
+    return {"p50": float(np.percentile(x, 50)), "p99": float(np.percentile(x, 99)),
+            "mean": float(x.mean()), "max": float(x.max())}
+
+
+def _job_spec(j, precision):
+    return dict(PARAMS, nx=j["L"], ny=j["L"], precision=precision, boundary=j["boundary"],
+                u_wall=j["u_wall"])
+
+
+def replay_trace(trace, budget_bytes, tick_s=0.02):
+    """Replays an arrival trace in real time against a serving pool: each job
+    is submitted when its arrival time has passed, the pool is advanced in
+    ticks of about tick_s seconds, and a job's time-to-result runs from its
+    arrival to the moment its observables and density fields are on the
+    host (the pool's clock)."""
+    from paper_0906_3611_amd import lb
+    pool = lb.Pool(budget_bytes, keep_fields=True, use_graph=True)
+    c0 = pool.stats()["clock"]
+    t0 = time.perf_counter()
+    pending = list(trace)
+    live, lat = {}, []
+    n_adv = 8
+    while pending or live:
+        now = time.perf_counter() - t0
+        while pending and pending[0]["t"] <= now:
+            j = pending.pop(0)
+            jid = pool.submit_noise(j["steps"], j["seed"], 0.5, 0.5, 0.01, **_job_spec(j, "fp32dev"))
+            live[jid] = j
+        st = pool.stats()
+        if st["queued"] + st["running"] == 0:
+            if pending:
+                time.sleep(max(0.0, min(0.005, pending[0]["t"] - (time.perf_counter() - t0))))
+            else:
+                pass
+        else:
+            ta = time.perf_counter()
+            pool.advance(n_adv)
+            dt = time.perf_counter() - ta
+            n_adv = int(min(4096, max(1, n_adv * tick_s / max(dt, 1e-4))))
+        for jid in list(live):
+            s = pool.state(jid)
+            if s == lb.LB_JOB_DONE:
+                t = pool.times(jid)
+                lat.append(t[2] - (c0 + live[jid]["t"]))
+                pool.release(jid)
+                del live[jid]
+            elif s == lb.LB_JOB_FAILED:
+                raise RuntimeError(f"job {jid} failed")
+    makespan = time.perf_counter() - t0
+    work = sum(j["L"] ** 2 * j["steps"] for j in trace)
+    st = pool.stats()
+    pool.close()
+    return {"jobs": len(trace), "latency_s": _percentiles(lat), "makespan_s": makespan,
+            "value": work / makespan / 1e6, "site_updates": work, "budget_bytes": budget_bytes,
+            "pool_ticks": st["ticks"]}
+
+
+def service_times(trace, precision, timed_steps=100):
+    """Per-job service time of a one-job-at-a-time GPU server: measured
+    per-step time of the job's own lattice (plain launches, 10 untimed
+    steps, then timed_steps timed with HIP events) times its step count,
+    plus the measured initialization and result transfer of that lattice."""
+    from paper_0906_3611_amd import lb
+    cache, out = {}, []
+    for j in trace:
+        key = (j["L"], j["boundary"], j["u_wall"])
+        if key not in cache:
+            kw = _job_spec(j, precision)
+            nx, ny = kw.pop("nx"), kw.pop("ny")
+            t0 = time.perf_counter()
+            lat = lb.Lattice(nx, ny, **kw)
+            lat.init_noise(j["seed"], 0.5, 0.5, 0.01)
+            t_init = time.perf_counter() - t0
+            lat.step(10)
+            ms = _timed(lat.stream, lambda: lat.step(timed_steps))
+            t0 = time.perf_counter()
+            lat.observables()
+            lat.fields()
+            t_fetch = time.perf_counter() - t0
+            lat.close()
+            cache[key] = (ms * 1e-3 / timed_steps, t_init + t_fetch)
+        per_step, fixed = cache[key]
+        out.append(per_step * j["steps"] + fixed)
+    return out
+
+
+def fifo(trace, service):
+    """First-in first-out single server: completion times and latencies."""
+    end, lat = 0.0, []
+    for j, s in zip(trace, service):
+        end = max(end, j["t"]) + s
+        lat.append(end - j["t"])
+    work = sum(j["L"] ** 2 * j["steps"] for j in trace)
+    span = end - trace[0]["t"]
+    return {"latency_s": _percentiles(lat), "makespan_s": span, "value": work / span / 1e6}
+
+
+def bench_serving(n_jobs=60, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5):
+    """Serving trace (Poisson arrivals, half Couette / half periodic, sides
+    log-uniform in [64, 2048], steps log-uniform in [1e3, 5e4], FP32 storage)
+    replayed in real time against the pool, then a rate-scaled variant at 0.7
+    of the capacity measured in the first replay.  Baselines: a sequential
+    first-in first-out server running one job at a time on the same GPU, in
+    FP64 and in FP32 storage, simulated from per-job service times measured
+    on this GPU."""
+    from paper_0906_3611_amd import inputs
+    budget = int(budget_gb * (1 << 30))
+    tr = inputs.serving_trace(n_jobs, rate, seed)
+    served = replay_trace(tr, budget)
+    print(f"# serving {n_jobs} jobs at {rate}/s: {served['value']:.0f} MLUPS, "
+          f"p50 {served['latency_s']['p50']:.2f} s p99 {served['latency_s']['p99']:.2f} s",
+          file=sys.stderr, flush=True)
+    out = {"workload": f"{n_jobs} Poisson arrivals at {rate}/s (seed {seed}), 50/50 Couette/periodic, "
+                       f"sides 64-2048, 1e3-5e4 steps, fp32dev, HBM budget {budget_gb} GiB",
+           "served": served,
+           "fifo_fp64": fifo(tr, service_times(tr, "fp64")),
+           "fifo_fp32dev": fifo(tr, service_times(tr, "fp32dev"))}
+    if n_scaled:
+        mean_work = sum(j["L"] ** 2 * j["steps"] for j in tr) / len(tr)
+        cap_rate = served["value"] * 1e6 / mean_work  # jobs/s at the measured throughput
+        rate2 = 0.7 * cap_rate
+        tr2 = inputs.serving_trace(n_scaled, rate2, seed + 1)
+        s2 = replay_trace(tr2, budget)
+        out["scaled_0p7"] = {"rate": rate2, "jobs": n_scaled, "served": s2,
+                             "fifo_fp64": fifo(tr2, service_times(tr2, "fp64"))}
+        print(f"# scaled trace at {rate2:.2f}/s: p50 {s2['latency_s']['p50']:.2f} s "
+              f"p99 {s2['latency_s']['p99']:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
 def traffic_for(precision, sites):
     """HBM bytes per step launch measured with rocprofv3 counters (scaled by
     a plain copy of known size), if they were taken on the current kernel."""
@@ -170,6 +425,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the 4096x1024 HBM-resident probe")
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 1 GiB copy")
+    ap.add_argument("--no-couette", action="store_true", help="skip the Couette channel runs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--ensemble", type=int, default=256, help="lattices in the batched ensemble")
+    ap.add_argument("--ensemble-steps", type=int, default=5000)
+    ap.add_argument("--serve-jobs", type=int, default=60, help="arrivals in the serving trace")
+    ap.add_argument("--serve-scaled-jobs", type=int, default=30,
+                    help="arrivals in the 0.7x-capacity trace (0: skip)")
+    ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="store HBM traffic per step from rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
@@ -217,6 +481,14 @@ def main():
                                         "achieved_gbs": pr["achieved_gbs"],
                                         "frac": pr["achieved_gbs"] / PEAK_HBM_GBS}
         print(f"# probe 4096x1024: {pr['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+
+    if not args.no_couette:
+        extra["couette"] = bench_couette()
+    if not args.no_batch:
+        extra["batched_ensemble"] = bench_batch(args.ensemble, args.ensemble_steps)
+    if not args.no_serve:
+        extra["serving"] = bench_serving(args.serve_jobs, 50.0, args.serve_scaled_jobs,
+                                         args.serve_budget_gb)
 
     sites = nx * ny
     pop_bytes = BYTES_PER_SITE[args.precision] * sites  # both population buffers (half each)

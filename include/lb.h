@@ -119,6 +119,24 @@ int lb_init(lb_lattice* lat, const double* rho_a, const double* rho_b, const dou
  * reference densities are mean_a and mean_b. */
 int lb_init_noise(lb_lattice* lat, uint64_t seed, double mean_a, double mean_b, double amp);
 
+/* Sharp two-phase emulsion (the mixed initial state of Sec. VI, in disc
+ * form): a union of random discs covering at least a fraction phi of the
+ * lattice holds (in_a, in_b), the rest (out_a, out_b).  Disc k has centre
+ * (nx U0, ny U1) and radius rmin + (rmax - rmin) U2 with U_j = (z >> 11)
+ * 2^-53, z output number 2^48 + 3k + j + 1 of SplitMix64 seeded with seed;
+ * a site is inside when its minimum-image periodic distance to a centre is
+ * <= that radius; discs are added until the covered count reaches
+ * phi nx ny.  Built on the host, then as lb_init with u = 0.  LB_E_INVAL for
+ * phi outside [0, 1], rmin <= 0 or rmax < rmin.  Synchronous. */
+int lb_init_discs(lb_lattice* lat, uint64_t seed, double phi, double rmin, double rmax,
+                  double in_a, double in_b, double out_a, double out_b);
+
+/* The densities lb_init_discs uses, into host rho_a, rho_b [ny][nx]
+ * (no lattice or device involved). */
+int lb_disc_fields(int32_t nx, int32_t ny, uint64_t seed, double phi, double rmin, double rmax,
+                   double in_a, double in_b, double out_a, double out_b, double* rho_a,
+                   double* rho_b);
+
 /* Enqueue n >= 0 time steps (Sec. II, Eq. (1)).  Asynchronous. */
 int lb_step(lb_lattice* lat, int64_t n);
 
@@ -172,6 +190,19 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
 int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
                   int32_t use_graph);
 
+/* Autotuner: time candidate launch shapes on the lattice's current state and
+ * keep the fastest.  Candidates are the default policy and forced segment
+ * heights of 8 to 256 rows with the current code variant, then the four
+ * prefetch / stream_stores variants at the best height; each runs 2 untimed
+ * steps and then `steps` (>= 2, rounded up to even) timed with HIP events on
+ * the lattice's stream.  The device state (populations, wall links, flags)
+ * and the step count are copied aside first and restored, so the evolution
+ * is unchanged; the wall-stress averages restart if the segment height
+ * changes.  Needs temporary device memory of the lattice's workspace size
+ * (LB_E_NOMEM otherwise).  out (may be NULL) receives the chosen shape,
+ * us_per_step (may be NULL) its time per step.  Synchronous. */
+int lb_autotune(lb_lattice* lat, int32_t steps, lb_launch_info* out, double* us_per_step);
+
 void lb_destroy(lb_lattice* lat);
 const char* lb_strerror(int status);
 const char* lb_last_error(const lb_lattice* lat);
@@ -199,6 +230,8 @@ int lb_batch_init(lb_batch* b, int32_t i, const double* rho_a, const double* rho
                   const double* ux, const double* uy);
 int lb_batch_init_noise(lb_batch* b, int32_t i, uint64_t seed, double mean_a, double mean_b,
                         double amp);
+int lb_batch_init_discs(lb_batch* b, int32_t i, uint64_t seed, double phi, double rmin,
+                        double rmax, double in_a, double in_b, double out_a, double out_b);
 /* Enqueue n steps of every lattice (LB_E_STATE until all are initialized). */
 int lb_batch_step(lb_batch* b, int64_t n);
 /* Observables of every lattice into out[0 .. n) (synchronizes). */
@@ -207,9 +240,15 @@ int lb_batch_get_fields(lb_batch* b, int32_t i, double* rho_a, double* rho_b, do
                         double* u_phys);
 int lb_batch_get_populations(lb_batch* b, int32_t i, double* f);
 int lb_batch_sync(lb_batch* b);
+/* Restart the wall-stress averages of every lattice (as lb_reset_averages). */
+int lb_batch_reset_averages(lb_batch* b);
 int lb_batch_get_launch_info(const lb_batch* b, lb_launch_info* out);
-/* As lb_set_launch without the segment height. */
-int lb_batch_set_launch(lb_batch* b, int32_t prefetch, int32_t stream_stores, int32_t use_graph);
+/* As lb_set_launch; seg_h applies to every lattice of the batch (equal
+ * tile heights balance the work of uneven lattices). */
+int lb_batch_set_launch(lb_batch* b, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
+                        int32_t use_graph);
+/* As lb_autotune, over the whole batch (one common segment height). */
+int lb_batch_autotune(lb_batch* b, int32_t steps, lb_launch_info* out, double* us_per_step);
 void lb_batch_destroy(lb_batch* b);
 const char* lb_batch_last_error(const lb_batch* b);
 

@@ -52,6 +52,7 @@ struct Engine {
   int ntiles = 0;
   int64_t step = 0;           // engine step count
   lbk::StepVariant variant{1, 0};
+  int seg_h = 0;              // forced segment height of every member (0: per-lattice default)
   bool use_graph = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two-step graphs by starting parity
   std::string err;
@@ -89,6 +90,10 @@ int engine_reset_averages(Engine& E);
 int engine_sync(Engine& E);
 int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32_t use_graph);
 int engine_regrid(Engine& E, int seg_h);
+// Time candidate launch shapes on the engine's own state and keep the
+// fastest; the state and step count are restored.  *us_per_step (may be
+// NULL) receives the chosen shape's time per step.
+int engine_autotune(Engine& E, int steps, double* us_per_step);
 void engine_info(const Engine& E, lb_launch_info* out);
 int64_t member_time(const Engine& E, int i);
 int member_index(const Engine& E, int64_t tag);
@@ -99,4 +104,18 @@ struct DeviceGuard {
   ~DeviceGuard();
 };
 
+// Disc-emulsion initial densities (lb_init_spec.hip).
+int disc_fields(int nx, int ny, uint64_t seed, double phi, double rmin, double rmax, double in_a,
+                double in_b, double out_a, double out_b, std::vector<double>& ra,
+                std::vector<double>& rb);
+
 }  // namespace lbe
+
+// Opaque handles of the C ABI: a lattice is an engine of one, a batch an
+// engine of n.
+struct lb_lattice {
+  lbe::Engine e;
+};
+struct lb_batch {
+  lbe::Engine e;
+};

@@ -475,6 +475,7 @@ int engine_add(Engine& E, const lb_params* p, int64_t tag, int* index) {
   }
   HIPCK(E, hipMemsetAsync(r, 0, rb, E.stream));
   E.m.push_back(make_member(p, (char*)r, true, tag));
+  if (E.seg_h) E.m.back().d.g = make_geometry(p, E.seg_h);
   E.bytes += rb;
   const int rc = retile(E);
   if (rc != LB_OK) {
@@ -712,10 +713,140 @@ int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32
 
 int engine_regrid(Engine& E, int seg_h) {
   DeviceGuard dg(E.device);
-  for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, seg_h);
+  E.seg_h = seg_h >= 4 ? seg_h : 0;
+  for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, E.seg_h);
   const int rc = retile(E);
   if (rc != LB_OK) return rc;
   return engine_reset_averages(E);
+}
+
+namespace {
+
+struct Events {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  ~Events() {
+    for (auto ev : e)
+      if (ev) (void)hipEventDestroy(ev);
+  }
+};
+
+// Per-member segment counts: two candidates that give the same counts are
+// the same launch.
+std::vector<int> seg_signature(const Engine& E, int seg_h) {
+  std::vector<int> s;
+  for (const auto& mm : E.m) s.push_back(make_geometry(&mm.p, seg_h).nsegs);
+  return s;
+}
+
+}  // namespace
+
+// Candidates: the default shape and forced segment heights 8..256 rows with
+// the current variant, then the four prefetch / streaming-store variants at
+// the best height.  Each candidate runs 2 untimed steps (capturing its graph
+// when graphs are on), then `steps` steps timed with HIP events on the
+// engine's stream.  The members' whole device regions (populations, wall
+// links, reduction slots, flag) are copied aside first and copied back at the
+// end, so the state is unchanged; if the chosen shape differs from the one
+// in use, the wall-stress averages restart (their slots follow the tiles).
+int engine_autotune(Engine& E, int steps, double* us_per_step) {
+  if (steps < 2) return E.fail(LB_E_INVAL, "autotune needs steps >= 2");
+  if (E.m.empty()) return E.fail(LB_E_STATE, "no lattices to tune");
+  for (auto& mm : E.m)
+    if (!mm.initialized) return E.fail(LB_E_STATE, "autotune before every lattice is initialized");
+  steps += steps & 1;  // whole two-step graphs
+  DeviceGuard dg(E.device);
+  size_t total = 0;
+  for (auto& mm : E.m) total += mm.region_bytes;
+  DevTmp save;
+  if (hipMalloc(&save.p, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return E.fail(LB_E_NOMEM, "no device memory for the autotuner's copy of the state");
+  }
+  size_t off = 0;
+  for (auto& mm : E.m) {
+    HIPCK(E, hipMemcpyAsync((char*)save.p + off, mm.region, mm.region_bytes, hipMemcpyDeviceToDevice,
+                            E.stream));
+    off += mm.region_bytes;
+  }
+  const int64_t step0 = E.step;
+  const int seg0 = E.seg_h;
+  const std::vector<int> sig0 = seg_signature(E, seg0);
+  Events ev;
+  HIPCK(E, hipEventCreate(&ev.e[0]));
+  HIPCK(E, hipEventCreate(&ev.e[1]));
+
+  auto run = [&](int seg_h, lbk::StepVariant v, double* us) -> int {
+    E.variant = v;
+    E.seg_h = seg_h;
+    for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, seg_h);
+    int rc = retile(E);  // also drops the graphs
+    if (rc != LB_OK) return rc;
+    rc = engine_step(E, 2);
+    if (rc != LB_OK) return rc;
+    HIPCK(E, hipEventRecord(ev.e[0], E.stream));
+    rc = engine_step(E, steps);
+    if (rc != LB_OK) return rc;
+    HIPCK(E, hipEventRecord(ev.e[1], E.stream));
+    HIPCK(E, hipEventSynchronize(ev.e[1]));
+    float ms = 0.f;
+    HIPCK(E, hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    *us = 1e3 * (double)ms / steps;
+    return LB_OK;
+  };
+
+  int ny_max = 0;
+  for (auto& mm : E.m) ny_max = std::max(ny_max, mm.p.ny);
+  std::vector<int> heights = {0};
+  for (int h : {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+    if (h < ny_max + 8) heights.push_back(h);
+  std::vector<std::vector<int>> seen;
+  int best_h = seg0;
+  lbk::StepVariant best_v = E.variant;
+  double best = 1e300;
+  int rc = LB_OK;
+  for (int h : heights) {
+    const auto sig = seg_signature(E, h);
+    if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+    seen.push_back(sig);
+    double us = 0.0;
+    rc = run(h, best_v, &us);
+    if (rc != LB_OK) break;
+    if (us < best) best = us, best_h = h;
+  }
+  if (rc == LB_OK) {
+    const lbk::StepVariant v1 = best_v;
+    for (int pf = 0; pf < 2 && rc == LB_OK; ++pf)
+      for (int nt = 0; nt < 2; ++nt) {
+        const lbk::StepVariant v{pf, nt};
+        if (v.prefetch == v1.prefetch && v.stream_stores == v1.stream_stores) continue;
+        double us = 0.0;
+        rc = run(best_h, v, &us);
+        if (rc != LB_OK) break;
+        if (us < best) best = us, best_v = v;
+      }
+  }
+  // restore the state under the chosen shape (or the original one on error)
+  if (rc != LB_OK) best_h = seg0;
+  E.variant = best_v;
+  E.seg_h = best_h;
+  for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, best_h);
+  const int rc2 = retile(E);
+  off = 0;
+  for (auto& mm : E.m) {
+    HIPCK(E, hipMemcpyAsync(mm.region, (char*)save.p + off, mm.region_bytes, hipMemcpyDeviceToDevice,
+                            E.stream));
+    off += mm.region_bytes;
+  }
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  E.step = step0;
+  if (rc != LB_OK) return rc;
+  if (rc2 != LB_OK) return rc2;
+  if (seg_signature(E, best_h) != sig0) {
+    const int r3 = engine_reset_averages(E);
+    if (r3 != LB_OK) return r3;
+  }
+  if (us_per_step) *us_per_step = best;
+  return LB_OK;
 }
 
 void engine_info(const Engine& E, lb_launch_info* out) {

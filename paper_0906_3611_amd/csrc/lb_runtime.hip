@@ -9,13 +9,6 @@
 using lbe::DeviceGuard;
 using lbe::Engine;
 
-struct lb_lattice {
-  Engine e;
-};
-struct lb_batch {
-  Engine e;
-};
-
 namespace {
 
 int validate_set(const lb_params* ps, int n) {
@@ -127,6 +120,13 @@ int lb_set_launch(lb_lattice* L, int32_t seg_h, int32_t prefetch, int32_t stream
   return seg_h >= 0 ? lbe::engine_regrid(L->e, seg_h) : LB_OK;
 }
 
+int lb_autotune(lb_lattice* L, int32_t steps, lb_launch_info* out, double* us_per_step) {
+  if (!L) return LB_E_INVAL;
+  const int rc = lbe::engine_autotune(L->e, steps, us_per_step);
+  if (rc == LB_OK && out) lbe::engine_info(L->e, out);
+  return rc;
+}
+
 /* ------------------------------ batches ------------------------------ */
 
 const char* lb_batch_last_error(const lb_batch* B) { return B ? B->e.err.c_str() : "null handle"; }
@@ -199,10 +199,23 @@ int lb_batch_get_launch_info(const lb_batch* B, lb_launch_info* out) {
   return LB_OK;
 }
 
-int lb_batch_set_launch(lb_batch* B, int32_t prefetch, int32_t stream_stores, int32_t use_graph) {
+int lb_batch_set_launch(lb_batch* B, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
+                        int32_t use_graph) {
   if (!B) return LB_E_INVAL;
   DeviceGuard dg(B->e.device);
-  return lbe::engine_set_variant(B->e, prefetch, stream_stores, use_graph);
+  lbe::engine_set_variant(B->e, prefetch, stream_stores, use_graph);
+  return seg_h >= 0 ? lbe::engine_regrid(B->e, seg_h) : LB_OK;
+}
+
+int lb_batch_reset_averages(lb_batch* B) {
+  return B ? lbe::engine_reset_averages(B->e) : LB_E_INVAL;
+}
+
+int lb_batch_autotune(lb_batch* B, int32_t steps, lb_launch_info* out, double* us_per_step) {
+  if (!B) return LB_E_INVAL;
+  const int rc = lbe::engine_autotune(B->e, steps, us_per_step);
+  if (rc == LB_OK && out) lbe::engine_info(B->e, out);
+  return rc;
 }
 
 }  // extern "C"

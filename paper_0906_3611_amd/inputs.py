@@ -114,3 +114,47 @@ def disc_fields(nx: int, ny: int, seed: int, phi: float, rmin: float = 6.0, rmax
     rho_a = np.where(m, in_a, out_a).astype(np.float64)
     rho_b = np.where(m, in_b, out_b).astype(np.float64)
     return rho_a, rho_b
+
+
+def _uniform_stream(seed: int, base: int, n: int) -> np.ndarray:
+    return uniform01(seed, np.uint64(base) + np.arange(1, n + 1, dtype=np.uint64))
+
+
+ENSEMBLE_COUNTER_BASE = 1 << 52
+TRACE_COUNTER_BASE = 1 << 53
+
+
+def ensemble_specs(n: int = 256, seed: int = 4, lmin: int = 128, lmax: int = 1024,
+                   ga_range=(-9.5, -8.5), phi_range=(0.5, 0.8)):
+    """An ensemble of independent square lattices: side L = round(exp(U[ln lmin,
+    ln lmax])), first-belt coupling G^a ~ U[ga_range] (both species), disc
+    volume fraction phi ~ U[phi_range].  Returns a list of dicts
+    (L, G_a, phi, seed) with a distinct disc seed per lattice."""
+    u = _uniform_stream(seed, ENSEMBLE_COUNTER_BASE, 3 * n).reshape(n, 3)
+    out = []
+    for k in range(n):
+        L = int(round(np.exp(np.log(lmin) + (np.log(lmax) - np.log(lmin)) * u[k, 0])))
+        ga = ga_range[0] + (ga_range[1] - ga_range[0]) * u[k, 1]
+        phi = phi_range[0] + (phi_range[1] - phi_range[0]) * u[k, 2]
+        out.append({"L": L, "G_a": float(ga), "phi": float(phi), "seed": seed * 100003 + k})
+    return out
+
+
+def serving_trace(n: int, rate: float, seed: int = 5, side=(64, 2048), steps=(1000, 50000),
+                  wall_speeds=(0.001, 0.005, 0.02)):
+    """A finite arrival trace: Poisson arrivals of the given rate (jobs/s),
+    half Couette jobs (wall speed drawn from wall_speeds) and half periodic,
+    square sides and step counts log-uniform in the given ranges.  Returns a
+    list of dicts (t, L, steps, boundary, u_wall, seed)."""
+    u = _uniform_stream(seed, TRACE_COUNTER_BASE, 5 * n).reshape(n, 5)
+    t = np.cumsum(-np.log1p(-u[:, 0]) / rate)
+    out = []
+    for k in range(n):
+        L = int(round(np.exp(np.log(side[0]) + (np.log(side[1]) - np.log(side[0])) * u[k, 1])))
+        st = int(round(np.exp(np.log(steps[0]) + (np.log(steps[1]) - np.log(steps[0])) * u[k, 2])))
+        couette = u[k, 3] < 0.5
+        uw = float(wall_speeds[min(int(u[k, 4] * len(wall_speeds)), len(wall_speeds) - 1)])
+        out.append({"t": float(t[k]), "L": L, "steps": st,
+                    "boundary": "couette" if couette else "periodic",
+                    "u_wall": uw if couette else 0.0, "seed": seed * 1000003 + k})
+    return out

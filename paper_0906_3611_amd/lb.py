@@ -68,6 +68,7 @@ def load():
     P = ctypes.POINTER
     vp, dp, i64, i32 = ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64, ctypes.c_int32
     h = ctypes.c_void_p
+    fd = ctypes.c_double
     sig = {
         "lb_abi_version": ([], ctypes.c_int),
         "lb_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -77,6 +78,8 @@ def load():
         "lb_init": ([h, dp, dp, dp, dp], ctypes.c_int),
         "lb_init_noise": ([h, ctypes.c_uint64, ctypes.c_double, ctypes.c_double, ctypes.c_double],
                           ctypes.c_int),
+        "lb_init_discs": ([h, ctypes.c_uint64] + [fd] * 7, ctypes.c_int),
+        "lb_disc_fields": ([i32, i32, ctypes.c_uint64] + [fd] * 7 + [dp, dp], ctypes.c_int),
         "lb_step": ([h, i64], ctypes.c_int),
         "lb_observables": ([h, P(lb_obs)], ctypes.c_int),
         "lb_get_fields": ([h, dp, dp, dp, dp], ctypes.c_int),
@@ -94,13 +97,17 @@ def load():
         "lb_batch_init": ([h, i32, dp, dp, dp, dp], ctypes.c_int),
         "lb_batch_init_noise": ([h, i32, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double], ctypes.c_int),
+        "lb_batch_init_discs": ([h, i32, ctypes.c_uint64] + [fd] * 7, ctypes.c_int),
         "lb_batch_step": ([h, i64], ctypes.c_int),
         "lb_batch_observables": ([h, P(lb_obs)], ctypes.c_int),
         "lb_batch_get_fields": ([h, i32, dp, dp, dp, dp], ctypes.c_int),
         "lb_batch_get_populations": ([h, i32, dp], ctypes.c_int),
         "lb_batch_sync": ([h], ctypes.c_int),
+        "lb_batch_reset_averages": ([h], ctypes.c_int),
         "lb_batch_get_launch_info": ([h, P(lb_launch_info)], ctypes.c_int),
-        "lb_batch_set_launch": ([h, i32, i32, i32], ctypes.c_int),
+        "lb_batch_set_launch": ([h, i32, i32, i32, i32], ctypes.c_int),
+        "lb_batch_autotune": ([h, i32, P(lb_launch_info), dp], ctypes.c_int),
+        "lb_autotune": ([h, i32, P(lb_launch_info), dp], ctypes.c_int),
         "lb_batch_destroy": ([h], None),
         "lb_batch_last_error": ([h], ctypes.c_char_p),
     }
@@ -130,6 +137,30 @@ def _f64(a, shape):
     if a.shape != shape:
         raise ValueError(f"expected shape {shape}, got {a.shape}")
     return a
+
+
+DISC_DEFAULTS = dict(rmin=6.0, rmax=12.0, in_a=1.2, in_b=0.05, out_a=0.05, out_b=1.2)
+
+
+def _disc_args(phi, kw):
+    a = dict(DISC_DEFAULTS)
+    unknown = set(kw) - set(a)
+    if unknown:
+        raise TypeError(f"unknown disc arguments {sorted(unknown)}")
+    a.update(kw)
+    return [float(phi)] + [float(a[k]) for k in ("rmin", "rmax", "in_a", "in_b", "out_a", "out_b")]
+
+
+def disc_fields(nx, ny, seed, phi, **kw):
+    """Host disc-emulsion densities of the library (lb_disc_fields):
+    (rho_a, rho_b), each (ny, nx) float64."""
+    L = load()
+    ra = np.empty((ny, nx), np.float64)
+    rb = np.empty((ny, nx), np.float64)
+    rc = L.lb_disc_fields(int(nx), int(ny), int(seed), *_disc_args(phi, kw), _dptr(ra), _dptr(rb))
+    if rc != 0:
+        raise LBError(rc, "lb_disc_fields: " + L.lb_strerror(rc).decode())
+    return ra, rb
 
 
 def make_params(nx, ny, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1),
@@ -243,6 +274,11 @@ class Lattice(_Handle):
         self._check(self._lib.lb_init_noise(self._h, int(seed), float(mean_a), float(mean_b),
                                             float(amp)), "lb_init_noise")
 
+    def init_discs(self, seed, phi, **kw):
+        """Disc emulsion (lb_init_discs); keyword defaults in DISC_DEFAULTS."""
+        self._check(self._lib.lb_init_discs(self._h, int(seed), *_disc_args(phi, kw)),
+                    "lb_init_discs")
+
     def step(self, n=1):
         self._check(self._lib.lb_step(self._h, int(n)), "lb_step")
 
@@ -287,6 +323,14 @@ class Lattice(_Handle):
         """Tuning knobs (lb_set_launch); -1 keeps the current choice."""
         self._check(self._lib.lb_set_launch(self._h, int(seg_h), int(prefetch), int(stream_stores),
                                             int(use_graph)), "lb_set_launch")
+
+    def autotune(self, steps=20) -> dict:
+        """lb_autotune: keep the fastest launch shape; returns it with its
+        time per step (us_per_step).  The state is unchanged."""
+        li, us = lb_launch_info(), ctypes.c_double()
+        self._check(self._lib.lb_autotune(self._h, int(steps), ctypes.byref(li), ctypes.byref(us)),
+                    "lb_autotune")
+        return dict(_info_dict(li), us_per_step=us.value)
 
 
 class Batch(_Handle):
@@ -333,6 +377,10 @@ class Batch(_Handle):
         self._check(self._lib.lb_batch_init_noise(self._h, int(i), int(seed), float(mean_a),
                                                   float(mean_b), float(amp)), "lb_batch_init_noise")
 
+    def init_discs(self, i, seed, phi, **kw):
+        self._check(self._lib.lb_batch_init_discs(self._h, int(i), int(seed), *_disc_args(phi, kw)),
+                    "lb_batch_init_discs")
+
     def step(self, n=1):
         self._check(self._lib.lb_batch_step(self._h, int(n)), "lb_batch_step")
 
@@ -359,15 +407,28 @@ class Batch(_Handle):
     def sync(self):
         self._check(self._lib.lb_batch_sync(self._h), "lb_batch_sync")
 
+    def reset_averages(self):
+        self._check(self._lib.lb_batch_reset_averages(self._h), "lb_batch_reset_averages")
+
     def launch_info(self) -> dict:
         li = lb_launch_info()
         self._check(self._lib.lb_batch_get_launch_info(self._h, ctypes.byref(li)),
                     "lb_batch_get_launch_info")
         return _info_dict(li)
 
-    def set_launch(self, prefetch=-1, stream_stores=-1, use_graph=-1):
-        self._check(self._lib.lb_batch_set_launch(self._h, int(prefetch), int(stream_stores),
-                                                  int(use_graph)), "lb_batch_set_launch")
+    def set_launch(self, seg_h=-1, prefetch=-1, stream_stores=-1, use_graph=-1):
+        """Tuning knobs (lb_batch_set_launch); seg_h applies to every lattice."""
+        self._check(self._lib.lb_batch_set_launch(self._h, int(seg_h), int(prefetch),
+                                                  int(stream_stores), int(use_graph)),
+                    "lb_batch_set_launch")
+
+    def autotune(self, steps=20) -> dict:
+        """lb_batch_autotune: keep the fastest launch shape; returns it with
+        its time per step (us_per_step)."""
+        li, us = lb_launch_info(), ctypes.c_double()
+        self._check(self._lib.lb_batch_autotune(self._h, int(steps), ctypes.byref(li),
+                                                ctypes.byref(us)), "lb_batch_autotune")
+        return dict(_info_dict(li), us_per_step=us.value)
 
 
 LB_JOB_QUEUED, LB_JOB_RUNNING, LB_JOB_DONE, LB_JOB_FAILED = 0, 1, 2, 3

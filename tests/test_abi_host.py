@@ -3,6 +3,7 @@ include/lb.h declares, and rejects invalid parameters on the host."""
 import ctypes
 import os
 
+import numpy as np
 import pytest
 
 from paper_0906_3611_amd import lb
@@ -64,3 +65,22 @@ def test_status_strings(L):
     assert L.lb_last_error(None) == b"null handle"
     assert L.lb_step(None, 1) == lb.LB_E_INVAL
     assert L.lb_current_step(None) == -1
+
+
+@pytest.mark.parametrize("nx,ny,seed,phi", [(64, 48, 1, 0.7), (17, 9, 3, 0.5), (8, 8, 2, 0.9),
+                                            (200, 60, 11, 1.0), (33, 5, 4, 0.0), (256, 192, 9, 0.6)])
+def test_library_disc_fields_match_the_input_generator(L, nx, ny, seed, phi):
+    """lb_disc_fields (host code of the library) reproduces the Python
+    generator bit for bit: both draw the same counters and take the same
+    minimum-image decisions in FP64."""
+    from paper_0906_3611_amd import inputs
+    ra, rb = inputs.disc_fields(nx, ny, seed, phi)
+    ga, gb = lb.disc_fields(nx, ny, seed, phi)
+    assert np.array_equal(ra, ga) and np.array_equal(rb, gb)
+
+
+def test_library_disc_fields_reject_bad_specs(L):
+    for kw in (dict(phi=1.5), dict(phi=-0.1), dict(phi=0.5, rmin=0.0), dict(phi=0.5, rmin=5.0, rmax=4.0)):
+        phi = kw.pop("phi")
+        with pytest.raises(lb.LBError):
+            lb.disc_fields(16, 16, 1, phi, **kw)

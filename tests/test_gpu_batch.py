@@ -137,3 +137,86 @@ def test_launch_variants_do_not_change_fields(precision):
         lat.init(ra, rb)
         lat.step(11)
         assert np.array_equal(lat.populations(), f_ref), (seg_h, pf, nt)
+
+
+@pytest.mark.parametrize("boundary", ["periodic", "couette"])
+def test_autotune_leaves_the_evolution_unchanged(boundary):
+    """lb_autotune times candidates on the live state, then restores it: the
+    run continues exactly as if it had not been called."""
+    lb = _lb()
+    nx, ny = 200, 96
+    u = 0.01 if boundary == "couette" else 0.0
+    ra, rb = inputs.noise_fields(nx, ny, 12, 0.5, 0.5, 0.05)
+    a = lb.Lattice(nx, ny, precision="fp32dev", boundary=boundary, u_wall=u, **BASE)
+    b = lb.Lattice(nx, ny, precision="fp32dev", boundary=boundary, u_wall=u, **BASE)
+    for lat in (a, b):
+        lat.init(ra, rb)
+        lat.step(7)
+    res = b.autotune(steps=4)
+    assert b.t == 7
+    assert res["us_per_step"] > 0 and res["ntiles"] >= 1
+    assert res["seg_h"] >= 1 and res["prefetch"] in (0, 1) and res["stream_stores"] in (0, 1)
+    a.step(9)
+    b.step(9)
+    assert np.array_equal(a.populations(), b.populations())
+    oa, ob = a.observables(), b.observables()
+    assert np.array_equal(oa["mass"], ob["mass"]) or np.allclose(oa["mass"], ob["mass"], rtol=1e-14)
+
+
+def test_batch_autotune_leaves_the_evolution_unchanged():
+    lb = _lb()
+    specs = _specs("fp32dev", "periodic")
+    a, b = lb.Batch(specs), lb.Batch(specs)
+    b.set_launch(use_graph=1)
+    for i, sp in enumerate(specs):
+        ra, rb = _fields_of(sp, 40 + i)
+        a.init(i, ra, rb)
+        b.init(i, ra, rb)
+    a.step(3)
+    b.step(3)
+    res = b.autotune(steps=4)
+    assert res["us_per_step"] > 0 and res["use_graph"] == 1
+    a.step(6)
+    b.step(6)
+    for i in range(len(specs)):
+        assert np.array_equal(a.populations(i), b.populations(i)), i
+
+
+def test_batch_common_segment_height():
+    lb = _lb()
+    specs = _specs("fp64", "couette")
+    b = lb.Batch(specs)
+    b.set_launch(seg_h=16)
+    info = b.launch_info()
+    assert info["seg_h"] <= 16  # 45 rows in 3 segments of 15
+    singles = []
+    for i, sp in enumerate(specs):
+        ra, rb = _fields_of(sp, 60 + i)
+        b.init(i, ra, rb)
+        kw = dict(sp)
+        nx, ny = kw.pop("nx"), kw.pop("ny")
+        lat = lb.Lattice(nx, ny, **kw)
+        lat.init(ra, rb)
+        singles.append(lat)
+    b.step(8)
+    for i, lat in enumerate(singles):
+        lat.step(8)
+        assert np.array_equal(b.populations(i), lat.populations()), i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_init_discs_equals_host_disc_fields(precision):
+    """lb_init_discs builds the emulsion in the library; the state equals
+    lb_init of the Python generator's densities bit for bit."""
+    lb = _lb()
+    nx, ny = 150, 70
+    ra, rb = inputs.disc_fields(nx, ny, 21, 0.6)
+    a = lb.Lattice(nx, ny, precision=precision, **BASE)
+    b = lb.Lattice(nx, ny, precision=precision, **BASE)
+    a.init(ra, rb)
+    b.init_discs(21, 0.6)
+    assert np.array_equal(a.populations(), b.populations())
+    bt = lb.Batch([dict(BASE, nx=nx, ny=ny, precision=precision)] * 2)
+    bt.init_discs(0, 21, 0.6)
+    bt.init(1, ra, rb)
+    assert np.array_equal(bt.populations(0), bt.populations(1))
