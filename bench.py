@@ -380,7 +380,11 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
             raise SystemExit(f"no matching dispatches in {path}")
         return statistics.median(vals)
 
-    step = lambda n: n.startswith("void lbk::") and "k_march<" in n and ", 0, " in n
+    def step(n):  # step-mode launches of the march kernel (template argument MODE = 0)
+        if "k_march<" not in n:
+            return False
+        args = n.split("k_march<", 1)[1].split(">", 1)[0].split(", ")
+        return len(args) == 7 and args[4] == "0"
     copy = lambda n: "copyBuffer" in n
     kib = copy_bytes / 1024
     f_scale = kib / per_dispatch(copy_fetch_csv, copy)

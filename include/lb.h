@@ -184,7 +184,8 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
  * the same apart from the tile-order of observable reductions when seg_h
  * changes).  Any argument < 0 keeps the current choice.
  *   seg_h: row-segment height (0 = default policy); resets the wall averages.
- *   prefetch: issue the next row's loads before the current collision.
+ *   prefetch: rows whose loads are in flight ahead of the current one
+ *     (0, 1 or 2; larger values mean 2).
  *   stream_stores: nontemporal population stores.
  *   use_graph: replay lb_step as captured two-step HIP graphs. */
 int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
@@ -192,8 +193,8 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
 
 /* Autotuner: time candidate launch shapes on the lattice's current state and
  * keep the fastest.  Candidates are the default policy and forced segment
- * heights of 8 to 256 rows with the current code variant, then the four
- * prefetch / stream_stores variants at the best height; each runs 2 untimed
+ * heights of 8 to 256 rows with the current code variant, then the six
+ * prefetch (0..2) / stream_stores variants at the best height; each runs 2 untimed
  * steps and then `steps` (>= 2, rounded up to even) timed with HIP events on
  * the lattice's stream.  The device state (populations, wall links, flags)
  * and the step count are copied aside first and restored, so the evolution

@@ -52,6 +52,7 @@ struct Engine {
   int ntiles = 0;
   int64_t step = 0;           // engine step count
   lbk::StepVariant variant{1, 0};
+  bool variant_forced = false;  // set by the caller or the autotuner: keep it
   int seg_h = 0;              // forced segment height of every member (0: per-lattice default)
   bool use_graph = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two-step graphs by starting parity

@@ -22,9 +22,10 @@ constexpr size_t kInfinityCacheBytes = 256ull << 20;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
-// Tiles: 64-column strips x row segments.  Aim for about 2048 wavefronts
-// (8 per CU) with segments of 8..64 rows: fewer, taller segments re-read
-// fewer ring rows, more keep HBM busy.  seg_h > 0 forces the segment height.
+// Tiles: 64-column strips x row segments.  Segments of 32 rows (4 ring
+// rows re-read per 32), shorter ones (down to 8 rows) where that leaves
+// fewer than about 2048 wavefronts (8 per CU) to keep HBM busy.
+// seg_h > 0 forces the segment height.
 lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   lbk::Geometry g{};
   g.nx = p->nx;
@@ -32,9 +33,8 @@ lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   g.pitch = (p->nx + lbk::kWave - 1) / lbk::kWave * lbk::kWave;  // strips start on a line
   g.row_elems = (long long)(g.pitch / lbk::kWave) * 18 * lbk::kWave;
   g.nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
-  int nsegs = (2048 + g.nstrips - 1) / g.nstrips;
+  int nsegs = std::max((p->ny + 31) / 32, (2048 + g.nstrips - 1) / g.nstrips);
   nsegs = std::min(nsegs, std::max(1, p->ny / 8));
-  nsegs = std::max(nsegs, (p->ny + 63) / 64);
   if (seg_h <= 0) {
     if (const char* e = std::getenv("LBSOFT_SEG_H")) seg_h = std::atoi(e);
   }
@@ -200,6 +200,8 @@ int reserve_shared(Engine& E, int members, int tiles) {
   return LB_OK;
 }
 
+void choose_default_variant(Engine& E);
+
 // Assign tile bases from the members' geometries and rebuild the tile map.
 int retile(Engine& E) {
   int base = 0;
@@ -212,6 +214,7 @@ int retile(Engine& E) {
   const int rc = reserve_shared(E, (int)E.m.size(), base);
   if (rc != LB_OK) return rc;
   E.ntiles = base;
+  choose_default_variant(E);
   if (E.m.size() > 1) {
     HIPCK(E, hipMemcpyAsync(E.d_tile_lattice, map.data(), map.size() * sizeof(int),
                             hipMemcpyHostToDevice, E.stream));
@@ -222,13 +225,17 @@ int retile(Engine& E) {
 }
 
 void choose_default_variant(Engine& E) {
-  // Defaults: prefetch for FP32 (registers allow it), streaming stores when
-  // the population buffers exceed the 256 MB Infinity Cache.
+  // Defaults (measured): when the population buffers exceed the 256 MB
+  // Infinity Cache, streaming stores and no prefetch (three FP32 waves per
+  // SIMD); when they fit, cached stores and a one-row prefetch for FP32.
+  if (E.variant_forced) return;
   size_t total_pop = 0;
   for (auto& mm : E.m) total_pop += 2 * mm.pop_bytes;
-  E.variant.prefetch = E.fp64 ? 0 : 1;
-  E.variant.stream_stores = total_pop > kInfinityCacheBytes ? 1 : 0;
-  if (const char* e = std::getenv("LBSOFT_PREFETCH")) E.variant.prefetch = std::atoi(e) ? 1 : 0;
+  const bool hbm = total_pop > kInfinityCacheBytes;
+  E.variant.prefetch = (E.fp64 || hbm) ? 0 : 1;
+  E.variant.stream_stores = hbm ? 1 : 0;
+  if (const char* e = std::getenv("LBSOFT_PREFETCH"))
+    E.variant.prefetch = std::max(0, std::min(std::atoi(e), 2));
   if (const char* e = std::getenv("LBSOFT_STREAM_STORES"))
     E.variant.stream_stores = std::atoi(e) ? 1 : 0;
 }
@@ -456,8 +463,7 @@ int engine_create_dynamic(Engine& E, bool fp64, bool walls, hipStream_t stream) 
   E.stream = stream;
   E.owns_shared = true;
   if (hipGetDevice(&E.device) != hipSuccess) return E.fail(LB_E_DEVICE, "no HIP device");
-  E.variant.prefetch = fp64 ? 0 : 1;
-  E.variant.stream_stores = 0;
+  choose_default_variant(E);
   return reserve_shared(E, 16, 4096);
 }
 
@@ -704,8 +710,9 @@ int engine_sync(Engine& E) {
 }
 
 int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32_t use_graph) {
-  if (prefetch >= 0) E.variant.prefetch = prefetch ? 1 : 0;
+  if (prefetch >= 0) E.variant.prefetch = std::min(prefetch, 2);
   if (stream_stores >= 0) E.variant.stream_stores = stream_stores ? 1 : 0;
+  if (prefetch >= 0 || stream_stores >= 0) E.variant_forced = true;
   if (use_graph >= 0) E.use_graph = use_graph != 0;
   drop_graphs(E);
   return LB_OK;
@@ -741,8 +748,8 @@ std::vector<int> seg_signature(const Engine& E, int seg_h) {
 }  // namespace
 
 // Candidates: the default shape and forced segment heights 8..256 rows with
-// the current variant, then the four prefetch / streaming-store variants at
-// the best height.  Each candidate runs 2 untimed steps (capturing its graph
+// the current variant, then the six prefetch-depth (0..2) / streaming-store
+// variants at the best height.  Each candidate runs 2 untimed steps (capturing its graph
 // when graphs are on), then `steps` steps timed with HIP events on the
 // engine's stream.  The members' whole device regions (populations, wall
 // links, reduction slots, flag) are copied aside first and copied back at the
@@ -775,6 +782,8 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   HIPCK(E, hipEventCreate(&ev.e[0]));
   HIPCK(E, hipEventCreate(&ev.e[1]));
 
+  const bool forced0 = E.variant_forced;
+  E.variant_forced = true;  // retile must keep each candidate's variant
   auto run = [&](int seg_h, lbk::StepVariant v, double* us) -> int {
     E.variant = v;
     E.seg_h = seg_h;
@@ -815,7 +824,7 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   }
   if (rc == LB_OK) {
     const lbk::StepVariant v1 = best_v;
-    for (int pf = 0; pf < 2 && rc == LB_OK; ++pf)
+    for (int pf = 0; pf < 3 && rc == LB_OK; ++pf)
       for (int nt = 0; nt < 2; ++nt) {
         const lbk::StepVariant v{pf, nt};
         if (v.prefetch == v1.prefetch && v.stream_stores == v1.stream_stores) continue;
@@ -828,6 +837,7 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   // restore the state under the chosen shape (or the original one on error)
   if (rc != LB_OK) best_h = seg0;
   E.variant = best_v;
+  E.variant_forced = true;
   E.seg_h = best_h;
   for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, best_h);
   const int rc2 = retile(E);
@@ -839,7 +849,10 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   }
   HIPCK(E, hipStreamSynchronize(E.stream));
   E.step = step0;
-  if (rc != LB_OK) return rc;
+  if (rc != LB_OK) {
+    E.variant_forced = forced0;
+    return rc;
+  }
   if (rc2 != LB_OK) return rc2;
   if (seg_signature(E, best_h) != sig0) {
     const int r3 = engine_reset_averages(E);

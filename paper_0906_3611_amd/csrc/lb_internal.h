@@ -83,7 +83,7 @@ struct LaunchArgs {
 
 // Code variants of the step kernel (tuning choices, same arithmetic).
 struct StepVariant {
-  int prefetch;       // issue the next row's pull before the current collision
+  int prefetch;       // rows pulled ahead of the current one (0, 1 or 2)
   int stream_stores;  // nontemporal population stores
 };
 

@@ -136,12 +136,25 @@ __device__ __forceinline__ float rcp_ct<float>(float x) {
 template <>
 __device__ __forceinline__ double rcp_ct<double>(double x) { return 1.0 / x; }
 
+// Global-memory (address space 1) views of device pointers.  The buffer
+// pointers of a lattice are read from its record in memory, so the compiler
+// cannot tell that they are global and would emit flat instructions; those
+// also count on the LDS/scalar wait counter (4 bits), which caps the loads a
+// wave keeps in flight and makes every LDS wait drain the HBM loads too.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T>* to_global(T* p) {
+  return (gmem<T>*)p;
+}
+
 // Loads and stores at a wave-uniform base plus a 32-bit per-lane byte
 // offset, so the address is an SGPR pair plus one VGPR (no 64-bit per-lane
 // address arithmetic).
 template <typename T>
 __device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (uint64_t)byte_off);
+  const gmem<const char>* b = (const gmem<const char>*)base;
+  return *(const gmem<const T>*)(b + byte_off);
 }
 // Population stores.  NT (streaming) stores keep the written buffer out of
 // the caches: right for lattices larger than the 256 MB Infinity Cache, whose
@@ -149,7 +162,7 @@ __device__ __forceinline__ T ld_at(const T* base, uint32_t byte_off) {
 // the Infinity Cache would serve.
 template <bool NT, typename T>
 __device__ __forceinline__ void st_at(T* base, uint32_t byte_off, T v) {
-  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (uint64_t)byte_off);
+  gmem<T>* p = (gmem<T>*)((gmem<char>*)base + byte_off);
   if (NT)
     __builtin_nontemporal_store(v, p);
   else
@@ -191,12 +204,12 @@ __device__ __forceinline__ void pull(const Geometry& g, const ST* __restrict__ s
       if (re == 0) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          f[s][wall_in_dir(0, j)] = (CT)wall_in[((0 * 2 + s) * 3 + j) * g.nx + col];
+          f[s][wall_in_dir(0, j)] = (CT)to_global(wall_in)[((0 * 2 + s) * 3 + j) * g.nx + col];
       }
       if (re == g.ny - 1) {
 #pragma unroll
         for (int j = 0; j < 3; ++j)
-          f[s][wall_in_dir(1, j)] = (CT)wall_in[((1 * 2 + s) * 3 + j) * g.nx + col];
+          f[s][wall_in_dir(1, j)] = (CT)to_global(wall_in)[((1 * 2 + s) * 3 + j) * g.nx + col];
       }
     }
   }
@@ -206,6 +219,13 @@ __device__ __forceinline__ void pull(const Geometry& g, const ST* __restrict__ s
 // deviation storage the LDS record holds deviations from the reference,
 // d_s = rho_s - rho_ref_s = sum_i delta_is and psi_s - psi(rho_ref_s), so
 // that stencil differences lose no digits to the common background.
+template <typename CT, bool DEV>
+__device__ __forceinline__ CT psi_of(const Params<CT, DEV>& P, int s, CT r) {
+  // select, not index: a lane-varying index would move P to scratch
+  if (DEV) return -(s ? P.pscale[1] : P.pscale[0]) * expm1_ct(-r * P.inv_rho0);
+  return P.rho0 * (CT(1) - exp_ct(-r * P.inv_rho0));
+}
+
 template <typename CT, bool DEV>
 __device__ __forceinline__ Fld<CT> make_fields(const Params<CT, DEV>& P, const CT (&f)[2][9]) {
   CT r[2];
@@ -219,14 +239,49 @@ __device__ __forceinline__ Fld<CT> make_fields(const Params<CT, DEV>& P, const C
   Fld<CT> o;
   o.ra = r[0];
   o.rb = r[1];
-  if (DEV) {
-    o.pa = -P.pscale[0] * expm1_ct(-r[0] * P.inv_rho0);
-    o.pb = -P.pscale[1] * expm1_ct(-r[1] * P.inv_rho0);
-  } else {
-    o.pa = P.rho0 * (CT(1) - exp_ct(-r[0] * P.inv_rho0));
-    o.pb = P.rho0 * (CT(1) - exp_ct(-r[1] * P.inv_rho0));
-  }
+  o.pa = psi_of<CT, DEV>(P, 0, r[0]);
+  o.pb = psi_of<CT, DEV>(P, 1, r[1]);
   return o;
+}
+
+// Ring columns of a strip: x0 - 2, x0 - 1, x0 + w, x0 + w + 1 (w = strip
+// width), wrapped periodically.
+__device__ __forceinline__ int ring_col(int rc, int x0, int width, int nx) {
+  return wrap(rc < 2 ? x0 - 2 + rc : x0 + width + (rc - 2), nx);
+}
+
+// Pull of the ring columns, shared by the whole wave: the 72 values
+// (4 columns x 2 species x 9 directions) of lattice row re are items
+// t = 4 (9 s + i) + rc, t = lane and t = 64 + lane (lanes 0..7).  The
+// sources follow the same rules as pull().
+template <typename ST, bool WALLS>
+__device__ __forceinline__ void ring_pull(const Geometry& g, const ST* __restrict__ src,
+                                          const ST* __restrict__ wall_in, int re, int x0,
+                                          int width, int lane, ST (&v)[2]) {
+  int rm, rp;
+  source_rows<WALLS>(re, g.ny, rm, rp);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int t = lane + kWave * h;
+    v[h] = ST(0);
+    if (h == 1 && lane >= 8) continue;
+    const int rc = t & 3, p = t >> 2;
+    const int s = p >= 9 ? 1 : 0, i = p - 9 * s;
+    const int c = ring_col(rc, x0, width, g.nx);
+    const int dy = cy(i);
+    if (WALLS && ((re == 0 && dy > 0) || (re == g.ny - 1 && dy < 0))) {
+      const int wl = re == 0 ? 0 : 1;
+      const int j = (i == 2 || i == 4) ? 0 : ((i == 5 || i == 7) ? 1 : 2);
+      v[h] = to_global(wall_in)[((wl * 2 + s) * 3 + j) * g.nx + c];
+    } else {
+      int sc = c - cx(i);
+      sc = sc < 0 ? sc + g.nx : (sc >= g.nx ? sc - g.nx : sc);
+      const int row = dy > 0 ? rm : (dy < 0 ? rp : re);
+      const long long off = (long long)row * g.row_elems + (long long)(sc >> 6) * (18 * kWave) +
+                            (long long)(p * kWave + (sc & 63));
+      v[h] = to_global(src)[off];
+    }
+  }
 }
 
 // The twelve +-c pairs of the 24 interaction neighbours: (cx, cy, class),
@@ -387,7 +442,7 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
         const CT po = wl ? post[o1] : post[o0];
         const int cxo = wl ? cx(o1) : cx(o0);
         const CT corr = CT(6) * wq<CT>(o0) * rho[sp] * ((CT)cxo * uwall);
-        wall_out[((wl * 2 + sp) * 3 + j) * g.nx + col] = (ST)(po - corr);
+        to_global(wall_out)[((wl * 2 + sp) * 3 + j) * g.nx + col] = (ST)(po - corr);
         const double full = (double)po + (DEV ? wq<double>(o0) * (double)P.rref[sp] : 0.0);
         mom += (double)cxo * (2.0 * full - (double)corr);
       }
@@ -410,12 +465,15 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // x0 - 2, x0 - 1, x0 + w, x0 + w + 1 (w = strip width).  Even segments
 // march up the rows, odd ones down, so two neighbouring segments reach
 // their shared ring rows at the same time and the second read hits L2.
-// PF = 1 issues the pull of the next row before the current collision.
+// PF > 0 keeps the pulls of the next PF rows in flight during the current
+// row's work (the loads of row k + PF are issued before the collision of
+// row k - 2).
 template <typename ST, typename CT, bool DEV, bool WALLS, int MODE, int PF, bool NT>
 __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
   constexpr int W = kWave + 4;
   constexpr int NSET = 3 + PF;
   __shared__ Fld<CT> ring[kRing * W];
+  __shared__ CT rstage[72];  // pulled ring-column values of the current row
   const int b = blockIdx.x;
   const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
   if (tile >= a.ntiles) return;
@@ -444,21 +502,18 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
   const uint32_t ob_c = in_row(col);
   const uint32_t ob_m = in_row(col == 0 ? nx - 1 : col - 1);
   const uint32_t ob_p = in_row(col == nx - 1 ? 0 : col + 1);
-  // ring column of lanes 0..3 and its LDS position
-  const int rl = lane & 3;
-  const int rcol = wrap(rl < 2 ? x0 - 2 + rl : x0 + width + (rl - 2), nx);
-  const int rpos = rl < 2 ? rl : width + rl;
-  const uint32_t rb_c = in_row(rcol);
-  const uint32_t rb_m = in_row(rcol == 0 ? nx - 1 : rcol - 1);
-  const uint32_t rb_p = in_row(rcol == nx - 1 ? 0 : rcol + 1);
+  // ring lanes 0..7: column rc = lane & 3 of species lane >> 2, at LDS
+  // position 0, 1 (left) or w + 2, w + 3 (right)
+  const int rcl = lane & 3, rsp = (lane >> 2) & 1;
+  const int rpos = rcl < 2 ? rcl : width + rcl;
 
   const Params<CT, DEV> P(D->c);
   const ST* __restrict__ src = (const ST*)D->buf[sel];
   const ST* __restrict__ wall_in = (const ST*)D->wall[sel];
   const Out<ST> out{g, (ST*)D->buf[sel ^ 1], (ST*)D->wall[sel ^ 1], a.fields, a.pops};
 
-  CT fr[NSET][2][9];
-  CT rg[2][9];
+  CT fr[NSET][2][9];  // pulled rows, set k % NSET for march row k
+  ST ri[NSET][2];     // this lane's ring items of those rows
   double acc[kNRed];
 #pragma unroll
   for (int m = 0; m < kNRed; ++m) acc[m] = 0.0;
@@ -472,29 +527,47 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
     if (WALLS) return r < 0 ? -1 - r : (r >= ny ? 2 * ny - 1 - r : r);  // mirrored ghost rows
     return r < 0 ? r + ny : (r >= ny ? r - ny : r);
   };
-  auto pull_row = [&](int k, CT (&dstf)[2][9]) {
+  auto pull_row = [&](int k, CT (&dstf)[2][9], ST (&dri)[2]) {
     const int re = lattice_row(k);
     pull<ST, CT, WALLS>(g, src, wall_in, re, ob_m, ob_c, ob_p, col, dstf);
-    if (lane < 4) pull<ST, CT, WALLS>(g, src, wall_in, re, rb_m, rb_c, rb_p, rcol, rg);
+    ring_pull<ST, WALLS>(g, src, wall_in, re, x0, width, lane, dri);
   };
 
-  if (PF) pull_row(0, fr[0]);
+  // PF rows are in flight ahead of the row whose fields are being formed
+  static_for<PF>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    if (q < K) pull_row(q, fr[q], ri[q]);
+  });
   for (int k0 = 0; k0 < K; k0 += NSET) {
     static_for<NSET>([&](auto J) {
       constexpr int j = decltype(J)::value;
       const int k = k0 + j;
       if (k >= K) return;
-      if (!PF) pull_row(k, fr[j]);
-      // fields of the pulled row into LDS slot k % 5
+      if (!PF) pull_row(k, fr[j], ri[j]);
+      // fields of the pulled row into LDS slot k % 5; the ring columns'
+      // values go through LDS to lanes 0..7, one (column, species) each,
+      // which sum them in the order make_fields uses
       const Fld<CT> fl = make_fields<CT, DEV>(P, fr[j]);
-      Fld<CT> flr;
-      if (lane < 4) flr = make_fields<CT, DEV>(P, rg);
+      rstage[lane] = (CT)ri[j][0];
+      if (lane < 8) rstage[kWave + lane] = (CT)ri[j][1];
       lds_fence();
       Fld<CT>* row = ring + (k % kRing) * W;
       if (active) row[lane + 2] = fl;
-      if (lane < 4) row[rpos] = flr;
+      if (lane < 8) {
+        CT acc = rstage[(rsp * 9) * 4 + rcl];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) acc += rstage[(rsp * 9 + i) * 4 + rcl];
+        const CT ps = psi_of<CT, DEV>(P, rsp, acc);
+        if (rsp) {
+          row[rpos].pb = ps;
+          row[rpos].rb = acc;
+        } else {
+          row[rpos].pa = ps;
+          row[rpos].ra = acc;
+        }
+      }
       lds_fence();
-      if (PF && k + 1 < K) pull_row(k + 1, fr[(j + 1) % NSET]);
+      if (PF && k + PF < K) pull_row(k + PF, fr[(j + PF) % NSET], ri[(j + PF) % NSET]);
       if (k >= 4 && active) {
         int slot[5];
 #pragma unroll
@@ -629,7 +702,7 @@ hipError_t launch_march(const LaunchArgs& a, bool fp64, bool walls, hipStream_t 
       hipLaunchKernelGGL((k_march<double, double, false, true, MODE, PF, NT>), grid, block, 0, st, a);
     else
       hipLaunchKernelGGL((k_march<double, double, false, false, MODE, PF, NT>), grid, block, 0, st, a);
-  } else if (MODE == kStep) {
+  } else if constexpr (MODE == kStep) {
     if (walls)
       hipLaunchKernelGGL((k_march<float, float, true, true, MODE, PF, NT>), grid, block, 0, st, a);
     else
@@ -672,7 +745,10 @@ hipError_t launch_init_any(const Geometry& g, const Coefs& c, bool fp64, bool wa
 
 hipError_t launch_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
                        hipStream_t st) {
-  if (v.prefetch)
+  if (v.prefetch >= 2)
+    return v.stream_stores ? launch_march<kStep, 2, true>(a, fp64, walls, st)
+                           : launch_march<kStep, 2, false>(a, fp64, walls, st);
+  if (v.prefetch == 1)
     return v.stream_stores ? launch_march<kStep, 1, true>(a, fp64, walls, st)
                            : launch_march<kStep, 1, false>(a, fp64, walls, st);
   return v.stream_stores ? launch_march<kStep, 0, true>(a, fp64, walls, st)

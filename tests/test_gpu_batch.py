@@ -129,7 +129,7 @@ def test_launch_variants_do_not_change_fields(precision):
     ref.init(ra, rb)
     ref.step(11)
     f_ref = ref.populations()
-    for seg_h, pf, nt in ((4, 0, 0), (8, 1, 1), (33, 0, 1), (96, 1, 0)):
+    for seg_h, pf, nt in ((4, 0, 0), (8, 1, 1), (33, 0, 1), (96, 1, 0), (16, 2, 1), (12, 2, 0)):
         lat = lb.Lattice(nx, ny, precision=precision, **BASE)
         lat.set_launch(seg_h=seg_h, prefetch=pf, stream_stores=nt)
         info = lat.launch_info()

@@ -10,6 +10,8 @@
 * Couette flow between moving walls: linear profile and wall stress rho nu du/dy.
 * Pure-repulsion bulk densities of a flat interface: Eq. (30) with the
   tau-renormalised rho_g of Eq. (29).
+* Laplace law for pure-repulsion droplets (the test of Sec. V A, Fig. 5):
+  the bulk-pressure jump across a circular interface falls as 1/R.
 """
 import math
 
@@ -181,3 +183,33 @@ def test_pure_repulsion_mixed_below_threshold():
         assert (spread > 0.5) == separates, (rho_mean, spread)
         if not separates:
             assert spread < 0.02 * 0.1
+
+
+def test_laplace_law_pure_repulsion_droplets():
+    """Droplets of the A-rich phase in the B-rich phase (cross force only,
+    rho_g^(tau) = 1, <rho> = 3) of radius R = 8, 11, 14, 17 in a 64^2 box: after
+    3000 steps the jump of the bulk pressure of Eqs. (12)/(14) between the
+    droplet centre and the far corner, times R, is the same for every radius
+    (Laplace, Delta P = sigma / R in 2D).  A wrong sign, weight or neighbour
+    of the cross force leaves no stable droplet or breaks the 1/R scaling."""
+    tau, rho_g, rho_mean, n = 1.0, 1.0, 3.0, 64
+    gab = theory.theta(tau) / rho_g
+    p = oracle.Params(nx=n, ny=n, tau=(tau, tau), rho0=1.0, Ga=(0, 0), Gr=(0, 0), Gab=gab)
+    hi, lo = theory.fixing_bulk_densities(rho_mean, rho_g)
+    y, x = np.mgrid[0:n, 0:n]
+    d = np.hypot(x - n / 2 + 0.5, y - n / 2 + 0.5)
+    c = n // 2
+    sig = []
+    for R in (8, 11, 14, 17):
+        inside = d <= R
+        ra, rb = np.where(inside, hi, lo), np.where(inside, lo, hi)
+        f, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 3000)
+        r = oracle.density(p, f)
+        assert r[0, c, c] > 2.5 and r[0, 0, 0] < 0.5  # the droplet survives
+        pin = theory.bulk_pressure(r[0, c - 1:c + 1, c - 1:c + 1].mean(),
+                                   r[1, c - 1:c + 1, c - 1:c + 1].mean(), 1.0, 0.0, 0.0, gab)
+        pout = theory.bulk_pressure(r[0, :2, :2].mean(), r[1, :2, :2].mean(), 1.0, 0.0, 0.0, gab)
+        assert pin > pout
+        sig.append((pin - pout) * R)
+    sig = np.array(sig)
+    assert np.ptp(sig) / sig.mean() < 0.03, sig
