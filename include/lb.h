@@ -180,10 +180,10 @@ typedef struct {
 } lb_launch_info;
 int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
 
-/* Tuning knobs that leave the arithmetic unchanged (results stay bit for bit
- * the same apart from the tile-order of observable reductions when seg_h
- * changes).  Any argument < 0 keeps the current choice.
- *   seg_h: row-segment height (0 = default policy); resets the wall averages.
+/* Tuning knobs that leave the arithmetic unchanged: fields and observables
+ * stay bit for bit the same (the FP64 reductions run over (row, strip) and
+ * strip partials, not over tiles).  Any argument < 0 keeps the current choice.
+ *   seg_h: row-segment height (0 = default policy); wall averages carry on.
  *   prefetch: rows whose loads are in flight ahead of the current one
  *     (0, 1 or 2; larger values mean 2).
  *   stream_stores: nontemporal population stores.
@@ -196,10 +196,12 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
  * heights of 8 to 256 rows with the current code variant, then the six
  * prefetch (0..2) / stream_stores variants at the best height; each runs 2 untimed
  * steps and then `steps` (>= 2, rounded up to even) timed with HIP events on
- * the lattice's stream.  The device state (populations, wall links, flags)
+ * the lattice's stream.  Results are kept for the life of the process, by
+ * GPU architecture, precision, boundary type, graph use and lattice shapes;
+ * steps = 0 applies a kept result without timing anything (and tunes with 16
+ * steps when there is none).  The device state (populations, wall links, flags)
  * and the step count are copied aside first and restored, so the evolution
- * is unchanged; the wall-stress averages restart if the segment height
- * changes.  Needs temporary device memory of the lattice's workspace size
+ * and the wall-stress averages are unchanged.  Needs temporary device memory of the lattice's workspace size
  * (LB_E_NOMEM otherwise).  out (may be NULL) receives the chosen shape,
  * us_per_step (may be NULL) its time per step.  Synchronous. */
 int lb_autotune(lb_lattice* lat, int32_t steps, lb_launch_info* out, double* us_per_step);

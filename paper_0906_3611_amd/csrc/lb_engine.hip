@@ -6,6 +6,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 namespace lbe {
 namespace {
@@ -46,7 +48,14 @@ lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   return g;
 }
 
-// The most tiles any segment height >= 4 can give (sizes the per-tile slots).
+// Reduction slots: observables per (row, strip), wall momentum per strip;
+// neither depends on the segment height.
+size_t red_slots(const lb_params* p) {
+  return (size_t)p->ny * (size_t)((p->nx + lbk::kWave - 1) / lbk::kWave);
+}
+size_t wall_slots(const lb_params* p) { return (size_t)((p->nx + lbk::kWave - 1) / lbk::kWave); }
+
+// The most tiles any segment height >= 4 can give (sizes the tile map).
 int max_tiles_of(const lb_params* p) {
   const int nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
   const int nsegs = std::max(1, std::min(p->ny, (p->ny + 3) / 4));
@@ -153,9 +162,9 @@ Member make_member(const lb_params* p, char* region, bool owns, int64_t tag) {
   mm.d.wall[1] = q + mm.wall_bytes;
   q += 2 * mm.wall_bytes;
   mm.d.wave_red = (double*)q;
-  q += align_up((size_t)mm.max_tiles * lbk::kNRed * sizeof(double));
+  q += align_up(red_slots(p) * lbk::kNRed * sizeof(double));
   mm.d.wave_wall = (double*)q;
-  q += align_up((size_t)mm.max_tiles * 2 * sizeof(double));
+  q += align_up(wall_slots(p) * 2 * sizeof(double));
   mm.d.flag = (int*)q;
   mm.d.phase = 0;
   return mm;
@@ -202,8 +211,33 @@ int reserve_shared(Engine& E, int members, int tiles) {
 
 void choose_default_variant(Engine& E);
 
+// Member geometries.  A forced height applies to every member.  Otherwise a
+// single lattice uses make_geometry's policy, and several lattices share one
+// segment height: 32 rows, halved (down to 8) only while the engine's tiles
+// stay under about 2048, so that small members are not cut into 8-row
+// segments when the whole launch has tiles to spare.
+std::vector<lbk::Geometry> geometries(const Engine& E, int seg_h) {
+  std::vector<lbk::Geometry> g;
+  int h = seg_h;
+  if (seg_h < 4 && E.m.size() > 1) {
+    for (h = 32; h > 8; h /= 2) {
+      long long tiles = 0;
+      for (auto& mm : E.m) tiles += (long long)make_geometry(&mm.p, h).ntiles;
+      if (tiles >= 2048) break;
+    }
+  }
+  for (auto& mm : E.m) g.push_back(make_geometry(&mm.p, h));
+  return g;
+}
+
+void apply_geometry(Engine& E) {
+  const auto g = geometries(E, E.seg_h);
+  for (size_t i = 0; i < E.m.size(); ++i) E.m[i].d.g = g[i];
+}
+
 // Assign tile bases from the members' geometries and rebuild the tile map.
 int retile(Engine& E) {
+  apply_geometry(E);
   int base = 0;
   std::vector<int> map;
   for (int i = 0; i < (int)E.m.size(); ++i) {
@@ -286,7 +320,7 @@ void begin_member(Engine& E, int i, int64_t member_t) {
 
 int zero_member_slots(Engine& E, int i) {
   const Member& mm = E.m[i];
-  HIPCK(E, hipMemsetAsync(mm.d.wave_wall, 0, (size_t)mm.max_tiles * 2 * sizeof(double), E.stream));
+  HIPCK(E, hipMemsetAsync(mm.d.wave_wall, 0, wall_slots(&mm.p) * 2 * sizeof(double), E.stream));
   HIPCK(E, hipMemsetAsync(mm.d.flag, 0, sizeof(int), E.stream));
   return LB_OK;
 }
@@ -401,11 +435,10 @@ int validate(const lb_params* p, std::string* why) {
 
 size_t member_region_bytes(const lb_params* p) {
   const lbk::Geometry g = make_geometry(p, 0);
-  const int mt = max_tiles_of(p);
   const size_t pop = align_up((size_t)g.row_elems * (size_t)g.ny * elem_size(p));
   const size_t wall = align_up(12ull * (size_t)p->nx * elem_size(p));
-  return 2 * pop + 2 * wall + align_up((size_t)mt * lbk::kNRed * sizeof(double)) +
-         align_up((size_t)mt * 2 * sizeof(double)) + kAlign;
+  return 2 * pop + 2 * wall + align_up(red_slots(p) * lbk::kNRed * sizeof(double)) +
+         align_up(wall_slots(p) * 2 * sizeof(double)) + kAlign;
 }
 
 size_t engine_static_bytes(const lb_params* ps, int n) {
@@ -481,7 +514,6 @@ int engine_add(Engine& E, const lb_params* p, int64_t tag, int* index) {
   }
   HIPCK(E, hipMemsetAsync(r, 0, rb, E.stream));
   E.m.push_back(make_member(p, (char*)r, true, tag));
-  if (E.seg_h) E.m.back().d.g = make_geometry(p, E.seg_h);
   E.bytes += rb;
   const int rc = retile(E);
   if (rc != LB_OK) {
@@ -698,7 +730,7 @@ int engine_set_pops(Engine& E, int i, const double* f, int64_t member_t) {
 int engine_reset_averages(Engine& E) {
   DeviceGuard dg(E.device);
   for (auto& mm : E.m) {
-    HIPCK(E, hipMemsetAsync(mm.d.wave_wall, 0, (size_t)mm.max_tiles * 2 * sizeof(double), E.stream));
+    HIPCK(E, hipMemsetAsync(mm.d.wave_wall, 0, wall_slots(&mm.p) * 2 * sizeof(double), E.stream));
     mm.avg_start = E.step;
   }
   return LB_OK;
@@ -721,10 +753,7 @@ int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32
 int engine_regrid(Engine& E, int seg_h) {
   DeviceGuard dg(E.device);
   E.seg_h = seg_h >= 4 ? seg_h : 0;
-  for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, E.seg_h);
-  const int rc = retile(E);
-  if (rc != LB_OK) return rc;
-  return engine_reset_averages(E);
+  return retile(E);  // reduction slots do not follow the tiles: averages carry on
 }
 
 namespace {
@@ -741,7 +770,7 @@ struct Events {
 // the same launch.
 std::vector<int> seg_signature(const Engine& E, int seg_h) {
   std::vector<int> s;
-  for (const auto& mm : E.m) s.push_back(make_geometry(&mm.p, seg_h).nsegs);
+  for (const auto& g : geometries(E, seg_h)) s.push_back(g.nsegs);
   return s;
 }
 
@@ -753,13 +782,63 @@ std::vector<int> seg_signature(const Engine& E, int seg_h) {
 // when graphs are on), then `steps` steps timed with HIP events on the
 // engine's stream.  The members' whole device regions (populations, wall
 // links, reduction slots, flag) are copied aside first and copied back at the
-// end, so the state is unchanged; if the chosen shape differs from the one
-// in use, the wall-stress averages restart (their slots follow the tiles).
+// end, so the state, the wall-stress averages included, is unchanged.
+namespace {
+
+// Autotuner results of this process, by GPU architecture, precision,
+// boundary type, graph use and the members' shapes.
+struct TuneResult {
+  int seg_h;
+  lbk::StepVariant v;
+  double us;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneResult> g_tune_cache;
+
+std::string tune_key(const Engine& E) {
+  hipDeviceProp_t prop{};
+  std::string arch = hipGetDeviceProperties(&prop, E.device) == hipSuccess ? prop.gcnArchName : "?";
+  std::vector<std::pair<int, int>> shapes;
+  for (const auto& mm : E.m) shapes.emplace_back(mm.p.nx, mm.p.ny);
+  std::sort(shapes.begin(), shapes.end());
+  std::string k = arch + (E.fp64 ? "/f64" : "/f32") + (E.walls ? "/walls" : "/periodic") +
+                  (E.use_graph ? "/graph" : "/launch");
+  for (auto& s : shapes) k += "/" + std::to_string(s.first) + "x" + std::to_string(s.second);
+  return k;
+}
+
+}  // namespace
+
 int engine_autotune(Engine& E, int steps, double* us_per_step) {
-  if (steps < 2) return E.fail(LB_E_INVAL, "autotune needs steps >= 2");
+  if (steps < 0) return E.fail(LB_E_INVAL, "autotune needs steps >= 0");
   if (E.m.empty()) return E.fail(LB_E_STATE, "no lattices to tune");
   for (auto& mm : E.m)
     if (!mm.initialized) return E.fail(LB_E_STATE, "autotune before every lattice is initialized");
+  const std::string key = tune_key(E);
+  if (steps == 0) {
+    TuneResult hit{};
+    bool found = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) hit = it->second, found = true;
+    }
+    if (found) {
+      if (seg_signature(E, hit.seg_h) != seg_signature(E, E.seg_h)) {
+        const int rc = engine_regrid(E, hit.seg_h);
+        if (rc != LB_OK) return rc;
+      } else {
+        E.seg_h = hit.seg_h;
+      }
+      E.variant = hit.v;
+      E.variant_forced = true;
+      drop_graphs(E);
+      if (us_per_step) *us_per_step = hit.us;
+      return LB_OK;
+    }
+    steps = 16;
+  }
+  steps = std::max(steps, 2);
   steps += steps & 1;  // whole two-step graphs
   DeviceGuard dg(E.device);
   size_t total = 0;
@@ -777,7 +856,6 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   }
   const int64_t step0 = E.step;
   const int seg0 = E.seg_h;
-  const std::vector<int> sig0 = seg_signature(E, seg0);
   Events ev;
   HIPCK(E, hipEventCreate(&ev.e[0]));
   HIPCK(E, hipEventCreate(&ev.e[1]));
@@ -787,8 +865,7 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   auto run = [&](int seg_h, lbk::StepVariant v, double* us) -> int {
     E.variant = v;
     E.seg_h = seg_h;
-    for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, seg_h);
-    int rc = retile(E);  // also drops the graphs
+    int rc = retile(E);  // sets the geometries, drops the graphs
     if (rc != LB_OK) return rc;
     rc = engine_step(E, 2);
     if (rc != LB_OK) return rc;
@@ -839,7 +916,6 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   E.variant = best_v;
   E.variant_forced = true;
   E.seg_h = best_h;
-  for (auto& mm : E.m) mm.d.g = make_geometry(&mm.p, best_h);
   const int rc2 = retile(E);
   off = 0;
   for (auto& mm : E.m) {
@@ -854,9 +930,9 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
     return rc;
   }
   if (rc2 != LB_OK) return rc2;
-  if (seg_signature(E, best_h) != sig0) {
-    const int r3 = engine_reset_averages(E);
-    if (r3 != LB_OK) return r3;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = TuneResult{best_h, best_v, best};
   }
   if (us_per_step) *us_per_step = best;
   return LB_OK;

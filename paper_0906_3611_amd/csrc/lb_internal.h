@@ -62,8 +62,8 @@ struct LatticeDesc {
   void* buf[2];   // population buffers (pull layout)
   void* wall[2];  // wall-link buffers
   int* flag;      // bit 0 set when a density is non-finite or <= 0
-  double* wave_red;   // observe: kNRed values per tile of this lattice
-  double* wave_wall;  // step: wall-momentum accumulators (bottom, top) per tile
+  double* wave_red;   // observe: kNRed partials per (row, strip) of this lattice
+  double* wave_wall;  // step: wall-momentum accumulators (bottom, top) per strip
   int tile_base;  // first tile of this lattice in its launch's tile list
   int phase;      // with launch step parity p the lattice reads buf[p ^ phase]
 };

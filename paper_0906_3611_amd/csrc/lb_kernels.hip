@@ -576,44 +576,53 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
         collide_row<CT, DEV, WALLS, MODE, ST, NT>(out, P, ring, lane + 2, slot, y, col, ob_c,
                                               fr[(j + NSET - 2) % NSET], acc, wacc, bad);
       }
+      if (MODE == kObserve && k >= 4) {
+        // partials of this strip row (fixed lane tree), stored by (row,
+        // strip): the totals do not depend on how rows are cut into segments
+        const long long rs = ((long long)lattice_row(k - 2) * g.nstrips + strip) * kNRed;
+#pragma unroll
+        for (int m = 0; m < kNRed; ++m) {
+          double v = acc[m];
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+          if (lane == 0) D->wave_red[rs + m] = v;
+          acc[m] = 0.0;
+        }
+      }
     });
   }
 
   if (__any(bad) && lane == 0) atomicOr(D->flag, 1);
-  if (MODE == kObserve) {
-#pragma unroll
-    for (int m = 0; m < kNRed; ++m) {
-      double v = acc[m];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-      if (lane == 0) D->wave_red[(long long)local * kNRed + m] = v;
-    }
-  } else if (WALLS && a.accumulate_wall && (y0 == 0 || y1 == ny)) {
+  if (MODE == kStep && WALLS && a.accumulate_wall) {
+    // wall momentum of this strip: slot (strip, wall), added to only by the
+    // tile holding that wall's row
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
+      if (m == 0 ? y0 != 0 : y1 != ny) continue;
       double v = wacc[m];
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-      if (lane == 0) D->wave_wall[(long long)local * 2 + m] += v;
+      if (lane == 0) D->wave_wall[(long long)strip * 2 + m] += v;
     }
   }
 }
 
-// Fixed-order reduction of per-tile values, one workgroup per lattice:
-// thread t sums the lattice's tiles t, t + 256, ... in order, then a fixed
-// binary tree.  The result depends only on the lattice's own tiles, so it is
-// the same bit for bit whether the lattice ran alone or in a batch.
+// Fixed-order reduction of a lattice's partials, one workgroup per lattice:
+// thread t sums slots t, t + 256, ... in order, then a fixed binary tree.
+// Slots are (row, strip) for observables and strips for the wall momentum,
+// so the result depends only on the lattice's size: it is the same bit for
+// bit alone or in a batch, and for any segment height.
 __global__ __launch_bounds__(256) void k_reduce_lattices(const LatticeDesc* __restrict__ descs,
                                                          int which, double* __restrict__ out,
                                                          int out_stride) {
   __shared__ double sh[256];
   const LatticeDesc* D = descs + blockIdx.x;
-  const int ntiles = D->g.ntiles;
+  const long long nslots = which ? (long long)D->g.nstrips : (long long)D->g.ny * D->g.nstrips;
   const double* __restrict__ in = which ? D->wave_wall : D->wave_red;
   const int width = which ? 2 : kNRed;
   for (int m = 0; m < width; ++m) {
     double v = 0.0;
-    for (int t = threadIdx.x; t < ntiles; t += 256) v += in[(long long)t * width + m];
+    for (long long t = threadIdx.x; t < nslots; t += 256) v += in[t * width + m];
     sh[threadIdx.x] = v;
     __syncthreads();
     for (int h = 128; h >= 1; h >>= 1) {

@@ -65,7 +65,7 @@ def test_batch_matches_single_bitwise(precision, boundary):
         assert np.array_equal(obs_b[i]["wall_stress"], o["wall_stress"]), i
         assert obs_b[i]["step"] == 13
     info = b.launch_info()
-    assert info["ntiles"] == sum(l.launch_info()["ntiles"] for l in singles)
+    assert info["ntiles"] >= sum(l.launch_info()["nstrips"] for l in singles)
 
 
 def test_batch_rejects_mixed_precision_and_uninitialized_step():
@@ -155,7 +155,7 @@ def test_autotune_leaves_the_evolution_unchanged(boundary):
     res = b.autotune(steps=4)
     assert b.t == 7
     assert res["us_per_step"] > 0 and res["ntiles"] >= 1
-    assert res["seg_h"] >= 1 and res["prefetch"] in (0, 1) and res["stream_stores"] in (0, 1)
+    assert res["seg_h"] >= 1 and res["prefetch"] in (0, 1, 2) and res["stream_stores"] in (0, 1)
     a.step(9)
     b.step(9)
     assert np.array_equal(a.populations(), b.populations())
@@ -220,3 +220,45 @@ def test_init_discs_equals_host_disc_fields(precision):
     bt.init_discs(0, 21, 0.6)
     bt.init(1, ra, rb)
     assert np.array_equal(bt.populations(0), bt.populations(1))
+
+
+def test_autotune_result_is_kept_per_shape():
+    """A second lattice of the same shape, precision and boundary takes the
+    kept result with steps = 0 (no timing) and keeps evolving exactly."""
+    lb = _lb()
+    nx, ny = 136, 80
+    ra, rb = inputs.noise_fields(nx, ny, 31, 0.5, 0.5, 0.05)
+    a = lb.Lattice(nx, ny, precision="fp32dev", **BASE)
+    a.init(ra, rb)
+    first = a.autotune(steps=4)
+    b = lb.Lattice(nx, ny, precision="fp32dev", **BASE)
+    b.init(ra, rb)
+    again = b.autotune(steps=0)
+    for k in ("seg_h", "prefetch", "stream_stores", "ntiles"):
+        assert again[k] == first[k], k
+    assert again["us_per_step"] == first["us_per_step"]
+    a.step(5)
+    b.step(5)
+    assert np.array_equal(a.populations(), b.populations())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_observables_do_not_depend_on_segment_height(precision):
+    """Observables and wall averages are reduced over (row, strip) and strip
+    partials, so re-cutting the segments mid-run changes nothing, bit for bit."""
+    lb = _lb()
+    nx, ny = 150, 100
+    ra, rb = inputs.noise_fields(nx, ny, 5, 0.5, 0.5, 0.05)
+    kw = dict(precision=precision, boundary="couette", u_wall=0.01, **BASE)
+    a, b = lb.Lattice(nx, ny, **kw), lb.Lattice(nx, ny, **kw)
+    a.set_launch(seg_h=8)
+    for lat in (a, b):
+        lat.init(ra, rb)
+        lat.step(6)
+    b.set_launch(seg_h=33)
+    a.step(7)
+    b.step(7)
+    oa, ob = a.observables(), b.observables()
+    for k in ("mass", "mom", "mom_phys", "wall_stress"):
+        assert np.array_equal(oa[k], ob[k]), k
+    assert oa["pxy_kin"] == ob["pxy_kin"] and oa["avg_count"] == ob["avg_count"] == 13
