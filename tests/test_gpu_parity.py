@@ -81,6 +81,30 @@ def test_fp64_short_run_ragged_sizes(nx, ny, boundary):
         assert err < 1e-13, (nx, ny, boundary, k, err)
 
 
+@pytest.mark.parametrize("boundary", ["periodic", "couette"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_general_parameters(precision, boundary):
+    """Unequal relaxation times (the 1/tau-weighted u' of Eq. (1)), tau != 1,
+    different couplings per species and another rho0, against the oracle."""
+    par = dict(tau=(0.8, 1.35), rho0=0.7, G_a=(-8.0, -9.5), G_r=(7.1, 8.3), G_AB=0.5)
+    nx, ny = 70, 50
+    u_wall = 0.01 if boundary == "couette" else 0.0
+    lat, p = make(nx, ny, precision=precision, boundary=boundary, u_wall=u_wall, **par)
+    ra, rb = inputs.noise_fields(nx, ny, 77, 0.45, 0.4, 0.05)
+    lat.init(ra, rb)
+    f = oracle.init_equilibrium(p, ra, rb)
+    done = 0
+    for k in (1, 10, 100):
+        lat.step(k - done)
+        f, _ = oracle.run(p, f, k - done)
+        done = k
+        tol = 1e-13 if precision == "fp64" else 2e-6
+        fl, ref = lat.fields(), oracle.fields(p, f)
+        for key in ("rho", "u", "uphys"):
+            err = np.abs(fl[key] - ref[key]).max()
+            assert err < tol, (k, key, err)
+
+
 def test_fp64_c1_parity_2000_steps():
     """C1: 64x64 periodic, rho = 0.5 +- 0.01, standard rho0 = 0.83 couplings."""
     lat, p = make(64, 64)
