@@ -41,7 +41,7 @@ class _CParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("walls", ctypes.c_int32),
                 ("pad_", ctypes.c_int32), ("tau", ctypes.c_double * 2), ("rho0", ctypes.c_double),
                 ("Ga", ctypes.c_double * 2), ("Gr", ctypes.c_double * 2), ("Gab", ctypes.c_double),
-                ("u_wall", ctypes.c_double)]
+                ("u_wall", ctypes.c_double), ("g_body", ctypes.c_double)]
 
 
 @dataclass
@@ -51,7 +51,9 @@ class Params:
     Ga, Gr: intra-species couplings G^a_s (first belt, w-weights) and G^r_s
     (both belts, p-weights); Gab: cross coupling G_AB; rho0: pseudopotential
     scale.  walls: halfway bounce-back walls below row 0 (x-velocity -u_wall)
-    and above row ny-1 (+u_wall); x stays periodic.
+    and above row ny-1 (+u_wall); x stays periodic.  g_body: amplitude of the
+    shear forcing of Sec. VIII, a force rho_s g_body sin(2 pi y / ny) along x
+    on each species.
     """
     nx: int
     ny: int
@@ -62,6 +64,7 @@ class Params:
     Gab: float = 0.405
     walls: bool = False
     u_wall: float = 0.0
+    g_body: float = 0.0
 
     def c(self) -> _CParams:
         cp = _CParams()
@@ -72,6 +75,7 @@ class Params:
         cp.Gr[0], cp.Gr[1] = float(self.Gr[0]), float(self.Gr[1])
         cp.Gab = float(self.Gab)
         cp.u_wall = float(self.u_wall)
+        cp.g_body = float(self.g_body)
         return cp
 
 
@@ -169,15 +173,17 @@ def fields(p: Params, f: np.ndarray) -> dict:
 
 
 def totals(p: Params, f: np.ndarray) -> dict:
-    """Global sums of the state: mass[2], mom[2], mom_phys[2], pxy_kin."""
+    """Global sums of the state: mass[2], mom[2], mom_phys[2], pxy_kin, the
+    first sine mode u_mode of the line-averaged x-velocity (R(t) times U0,
+    Sec. VIII Eq. (68)) and the interface indicator i_ab (Eq. (69))."""
     f = _f64(f)
-    out = np.zeros(7)
+    out = np.zeros(9)
     cp = p.c()
     rc = lib().lbref_totals(ctypes.byref(cp), _ptr(f), _ptr(out))
     if rc != 0:
         raise MemoryError
     return {"mass": out[0:2].copy(), "mom": out[2:4].copy(), "mom_phys": out[4:6].copy(),
-            "pxy_kin": float(out[6])}
+            "pxy_kin": float(out[6]), "u_mode": float(out[7]), "i_ab": float(out[8])}
 
 
 def density(p: Params, f: np.ndarray) -> np.ndarray:

@@ -91,7 +91,13 @@ typedef struct {
   double Gr[NS];    /* G^r_s, belt-1+2 intra-species coupling (Eq. (2)) */
   double Gab;       /* G_AB = G_BA, belt-1 cross coupling (Eq. (2)) */
   double u_wall;    /* wall speed for walls == 1 */
+  double g_body;    /* amplitude of the volumetric shear forcing of Sec. VIII:
+                       each species feels rho_s g(y) along x with
+                       g(y) = g_body sin(2 pi y / ny), the force that drives
+                       U_x = U0 sin(k y), k = 2 pi / ny (first mode) */
 } lbref_params;
+
+static const double TWO_PI = 6.283185307179586476925286766559;
 
 #define IDX(p, y, x) ((size_t)(y) * (size_t)(p)->nx + (size_t)(x))
 #define FI(p, f, s, i, y, x) \
@@ -166,11 +172,13 @@ void lbref_force(const lbref_params* p, const double* rho, const double* psi, do
           }
         }
         const size_t k = IDX(p, y, x);
+        const double gy = p->g_body * sin(TWO_PI * (double)y / (double)p->ny);
         for (int a = 0; a < 2; ++a) {
           const double Fa = -p->Ga[s] * ps[k] * att[a];
           const double Fr = -p->Gr[s] * ps[k] * rep1[a] - p->Gr[s] * ps[k] * rep2[a];
           const double FX = -(1.0 / (p->rho0 * p->rho0)) * rs[k] * crs[a];
-          F[((size_t)s * 2 + a) * n + k] = Fa + Fr + FX;
+          const double Fb = a == 0 ? rs[k] * gy : 0.0; /* body force (Sec. VIII) */
+          F[((size_t)s * 2 + a) * n + k] = Fa + Fr + FX + Fb;
         }
       }
   }
@@ -377,7 +385,14 @@ int lbref_fields(const lbref_params* p, const double* f, double* rho, double* u,
  *   out[0..1] species masses sum_r rho_s,
  *   out[2..3] total momentum sum_r sum_s j_s,
  *   out[4..5] total momentum with half the force, sum_r (sum_s j_s + F/2),
- *   out[6]    kinetic stress sum_r sum_s sum_i f_is c_ix c_iy (Sec. III, Eq. (10)). */
+ *   out[6]    kinetic stress sum_r sum_s sum_i f_is c_ix c_iy (Sec. III, Eq. (10)),
+ *   out[7]    first sine mode of the line-averaged x-velocity (Sec. VIII,
+ *             Eq. (68)): (2 / ny) sum_y sin(2 pi y / ny) Ubar(y), Ubar(y) =
+ *             sum_x uphys_x / nx; divided by U0 it is the response R(t),
+ *   out[8]    interface indicator I_AB = - sum_r grad rho_A . grad rho_B
+ *             (Sec. VIII, Eq. (69)), with the lattice gradient
+ *             grad phi(r) = (1 / c_s^2) sum_{i=1..8} w_i phi(r + c_i) c_i over
+ *             the force stencil's neighbours (wrapped, or mirrored at walls). */
 int lbref_totals(const lbref_params* p, const double* f, double* out) {
   const size_t n = nsites(p);
   double* rho = (double*)malloc(10 * n * sizeof(double));
@@ -406,6 +421,27 @@ int lbref_totals(const lbref_params* p, const double* f, double* out) {
         out[5] += jy + 0.5 * F[((size_t)s * 2 + 1) * n + k];
         out[6] += pxy;
       }
+  out[7] = 0.0;
+  for (int y = 0; y < p->ny; ++y) {
+    double ubar = 0.0;
+    for (int x = 0; x < p->nx; ++x) ubar += uphys[IDX(p, y, x)];
+    ubar /= (double)p->nx;
+    out[7] += sin(TWO_PI * (double)y / (double)p->ny) * ubar;
+  }
+  out[7] *= 2.0 / (double)p->ny;
+  out[8] = 0.0;
+  for (int y = 0; y < p->ny; ++y)
+    for (int x = 0; x < p->nx; ++x) {
+      double g[NS][2] = {{0, 0}, {0, 0}};
+      for (int i = 1; i <= 8; ++i) {
+        const size_t nb = IDX(p, stencil_row(p, y + EY[i]), wrap_x(p, x + EX[i]));
+        for (int s = 0; s < NS; ++s) {
+          g[s][0] += WE[i] * rho[(size_t)s * n + nb] * EX[i] / CS2;
+          g[s][1] += WE[i] * rho[(size_t)s * n + nb] * EY[i] / CS2;
+        }
+      }
+      out[8] -= g[0][0] * g[1][0] + g[0][1] * g[1][1];
+    }
   free(rho);
   return 0;
 }

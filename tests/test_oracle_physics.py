@@ -12,6 +12,10 @@
   tau-renormalised rho_g of Eq. (29).
 * Laplace law for pure-repulsion droplets (the test of Sec. V A, Fig. 5):
   the bulk-pressure jump across a circular interface falls as 1/R.
+* Shear forcing of Sec. VIII: the steady Kolmogorov flow of a non-interacting
+  mixture (exact on the lattice at tau = 1, second order in k otherwise),
+  its first-mode response (Eq. (68)), and the interface indicator (Eq. (69))
+  of a sine profile.
 """
 import math
 
@@ -213,3 +217,59 @@ def test_laplace_law_pure_repulsion_droplets():
         sig.append((pin - pout) * R)
     sig = np.array(sig)
     assert np.ptp(sig) / sig.mean() < 0.03, sig
+
+
+def _kolmogorov_mode(ny, tau, g, steps, nx=4):
+    p = oracle.Params(nx=nx, ny=ny, tau=(tau, tau), rho0=1.0, Ga=(0, 0), Gr=(0, 0), Gab=0.0,
+                      g_body=g)
+    ra, rb = np.full((ny, nx), 0.6), np.full((ny, nx), 0.4)
+    f, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), steps)
+    return p, f
+
+
+def test_kolmogorov_flow_exact_at_tau_one():
+    """tau = 1, no interactions: every step sets f* = f^eq(rho, u + g), and
+    streaming maps the x-velocity mode sin(k y) to (1 - a) times itself with
+    a = (1 - cos k)/3 (sum of w_i c_ix^2 over the three rows).  The steady
+    state is u = (1 - a)(u + g), i.e. u = g (1 - a)/a before the half-force
+    shift and u_phys = u + g/2 = g (1/a - 1/2) after it, for every y."""
+    ny, g = 64, 1e-6
+    p, f = _kolmogorov_mode(ny, 1.0, g, 15000)
+    k = 2.0 * math.pi / ny
+    a = (1.0 - math.cos(k)) / 3.0
+    amp = g * (1.0 / a - 0.5)
+    ux = oracle.fields(p, f)["uphys"][0]
+    prof = amp * np.sin(k * np.arange(ny))[:, None]
+    assert np.abs(ux - prof).max() < 1e-8 * amp
+    t = oracle.totals(p, f)
+    assert t["u_mode"] == pytest.approx(amp, rel=1e-8)
+    assert abs(t["i_ab"]) < 1e-20
+
+
+def test_kolmogorov_flow_second_order_in_k():
+    """tau != 1: the steady first mode approaches the continuum U0 =
+    g / (nu k^2), nu = c_s^2 (tau - 1/2), with an O(k^2) lattice error that
+    falls about fourfold when ny doubles."""
+    tau, g = 1.3, 1e-6
+    nu = CS2 * (tau - 0.5)
+    dev = []
+    for ny, steps in ((64, 16000), (128, 40000)):
+        p, f = _kolmogorov_mode(ny, tau, g, steps)
+        k = 2.0 * math.pi / ny
+        dev.append(oracle.totals(p, f)["u_mode"] / (g / (nu * k * k)) - 1.0)
+    assert abs(dev[0]) < 5e-3, dev
+    assert abs(dev[1]) < abs(dev[0]) / 3.0, dev
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_interface_indicator_of_a_sine_profile(walls):
+    """rho_A = 0.5 + e sin(k x), rho_B = 0.5 - e sin(k x): the lattice gradient
+    (1/c_s^2) sum_i w_i phi(r + c_i) c_i of sin(k x) is sin(k) cos(k x), so
+    I_AB = e^2 sin(k)^2 sum_r cos(k x)^2 = e^2 sin(k)^2 nx ny / 2."""
+    nx, ny, e = 32, 9, 0.03
+    k = 2.0 * math.pi / nx
+    p = oracle.Params(nx=nx, ny=ny, walls=walls)
+    s = np.sin(k * np.arange(nx))[None, :].repeat(ny, axis=0)
+    f = oracle.init_equilibrium(p, 0.5 + e * s, 0.5 - e * s)
+    t = oracle.totals(p, f)
+    assert t["i_ab"] == pytest.approx(e * e * math.sin(k) ** 2 * nx * ny / 2.0, rel=1e-12)
