@@ -164,6 +164,38 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
                               "points": curve}}
 
 
+def bench_kolmogorov(speeds=(0.005, 0.01, 0.02, 0.03, 0.04, 0.05), n=128,
+                     checkpoints=(1000, 10000, 100000), seed=10):
+    """The shear protocol of Sec. VIII (Figs. 10, 11): 128^2 periodic, the
+    standard rho0 = 0.7 couplings, <rho_A> = <rho_B> = 0.612 +- 0.01, tau = 1,
+    body force driving U_x = U0 sin(2 pi y / n), one lattice per U0 in one
+    batch (graph replay, autotuned).  Reports the response R = u_mode / U0
+    (Eq. (68)) and the interface indicator I_AB (Eq. (69)) at each checkpoint."""
+    from paper_0906_3611_amd import inputs, lb
+    par = dict(tau=(1.0, 1.0), rho0=0.7, G_a=(-15.0, -14.0), G_r=(14.1, 13.1), G_AB=0.405)
+    specs = [dict(par, nx=n, ny=n, precision="fp32dev", body_force=lb.kolmogorov_force(U, n))
+             for U in speeds]
+    b = lb.Batch(specs)
+    ra, rb = inputs.noise_fields(n, n, seed, 0.612, 0.612, 0.01)
+    for i in range(len(speeds)):
+        b.init(i, ra, rb)
+    b.set_launch(use_graph=1)
+    tuned = b.autotune(steps=20)
+    rows, done, ms = [], 0, 0.0
+    for t in checkpoints:
+        ms += _timed(b.stream, lambda: b.step(t - done))
+        done = t
+        obs = b.observables()
+        rows.append({"t": t, "R": [o["u_mode"] / U for o, U in zip(obs, speeds)],
+                     "I_AB": [o["i_ab"] for o in obs]})
+    b.close()
+    return {"workload": f"{len(speeds)} lattices {n}x{n}, rho0 = 0.7 standard set, <rho> = 0.612 +- 0.01 "
+                        f"(seed {seed}), tau = 1, fp32dev, shear forcing U0 = {list(speeds)}",
+            "value": len(speeds) * n * n * done / (ms * 1e-3) / 1e6, "steps": done,
+            "launch": {k: tuned[k] for k in ("seg_h", "ntiles", "prefetch", "stream_stores")},
+            "U0": list(speeds), "checkpoints": rows}
+
+
 def bench_batch(n=256, steps=5000, seed=4, tune_steps=10):
     """Ensemble of n independent square lattices (sides log-uniform in
     [128, 1024], G^a in [-9.5, -8.5], disc fraction in [0.5, 0.8]) in FP32
@@ -430,6 +462,7 @@ def main():
     ap.add_argument("--no-probe", action="store_true", help="skip the 4096x1024 HBM-resident probe")
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 1 GiB copy")
     ap.add_argument("--no-couette", action="store_true", help="skip the Couette channel runs")
+    ap.add_argument("--no-kolmogorov", action="store_true", help="skip the shear-forcing protocol")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--ensemble", type=int, default=256, help="lattices in the batched ensemble")
@@ -488,6 +521,10 @@ def main():
 
     if not args.no_couette:
         extra["couette"] = bench_couette()
+    if not args.no_kolmogorov:
+        extra["kolmogorov"] = bench_kolmogorov()
+        print(f"# kolmogorov batch: {extra['kolmogorov']['value']:.0f} MLUPS", file=sys.stderr,
+              flush=True)
     if not args.no_batch:
         extra["batched_ensemble"] = bench_batch(args.ensemble, args.ensemble_steps)
     if not args.no_serve:

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 1
+#define LB_ABI_VERSION 2
 
 enum {
   LB_OK = 0,
@@ -70,6 +70,11 @@ typedef struct {
   double G_r[2];
   double G_AB;
   double u_wall;      /* wall x-speed for LB_COUETTE_Y (top +u_wall, bottom -u_wall) */
+  double body_force;  /* amplitude g of the shear forcing of Sec. VIII: each
+                         species feels rho_s g sin(2 pi y / ny) along x (the
+                         drive of U_x = U0 sin(k y), k = 2 pi / ny; a
+                         non-interacting fluid reaches U0 = g / (nu k^2)).
+                         0: no body force.  Must be finite. */
   double rho_ref[2];  /* LB_FP32_DEV reference densities; <= 0 selects the
                          lattice mean of the fields given to lb_init() */
   void* device_buffer;   /* optional caller-owned device workspace (e.g. the
@@ -92,6 +97,14 @@ typedef struct {
   int64_t avg_count;     /* number of steps in that average */
   int32_t flags;         /* bit 0: instability seen */
   int32_t pad_;
+  double u_mode;         /* first sine mode of the line-averaged x-velocity,
+                            (2 / (nx ny)) sum_r u_phys,x sin(2 pi y / ny);
+                            divided by U0 it is the response R(t) of
+                            Sec. VIII, Eq. (68) */
+  double i_ab;           /* interface indicator -sum_r grad rho_A . grad rho_B
+                            (Sec. VIII, Eq. (69)); grad phi = (1 / c_s^2)
+                            sum_{i=1..8} w_i phi(r + c_i) c_i over the force
+                            stencil's neighbours (mirrored at walls) */
 } lb_obs;
 
 typedef struct lb_lattice lb_lattice;

@@ -10,6 +10,7 @@
 #include <mutex>
 
 namespace lbe {
+static_assert(lbk::kNRed + 2 <= 16, "reduction output rows hold 16 doubles");
 namespace {
 
 constexpr size_t kAlign = 256;
@@ -84,6 +85,8 @@ void round_coefs(lbk::Coefs& c) {
   c.f_rho0 = (float)c.rho0;
   c.f_inv_rho0 = (float)c.inv_rho0;
   c.f_u_wall = (float)c.u_wall;
+  c.f_g_body = (float)c.g_body;
+  c.f_inv_ny2 = (float)c.inv_ny2;
 }
 
 lbk::Coefs make_coefs(const lb_params* p) {
@@ -104,6 +107,8 @@ lbk::Coefs make_coefs(const lb_params* p) {
   c.rho0 = p->rho0;
   c.inv_rho0 = 1.0 / p->rho0;
   c.u_wall = p->u_wall;
+  c.g_body = p->body_force;
+  c.inv_ny2 = 2.0 / (double)p->ny;
   round_coefs(c);
   return c;
 }
@@ -398,6 +403,8 @@ void fill_obs(const Engine& E, int i, const double* h, int flag, lb_obs* out) {
     out->wall_stress[0] = h[lbk::kNRed + 0] / (double)out->avg_count / (double)mm.d.g.nx;
     out->wall_stress[1] = h[lbk::kNRed + 1] / (double)out->avg_count / (double)mm.d.g.nx;
   }
+  out->u_mode = h[7] * 2.0 / ((double)mm.d.g.nx * (double)mm.d.g.ny);
+  out->i_ab = h[8];
   out->flags = flag;
 }
 
@@ -430,6 +437,7 @@ int validate(const lb_params* p, std::string* why) {
   if (!is_finite(p->rho0) || !(p->rho0 > 0)) return bad("rho0 must be > 0");
   if (!is_finite(p->G_AB)) return bad("G_AB must be finite");
   if (!is_finite(p->u_wall)) return bad("u_wall must be finite");
+  if (!is_finite(p->body_force)) return bad("body_force must be finite");
   return LB_OK;
 }
 

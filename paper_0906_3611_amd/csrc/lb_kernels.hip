@@ -83,7 +83,7 @@ struct Params;
 
 template <bool DEV>
 struct Params<double, DEV> {
-  double k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw;
+  double k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw, g, iny2;
   __device__ explicit Params(const Coefs& c) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -100,12 +100,14 @@ struct Params<double, DEV> {
     rho0 = c.rho0;
     inv_rho0 = c.inv_rho0;
     uw = c.u_wall;
+    g = c.g_body;
+    iny2 = c.inv_ny2;
   }
 };
 
 template <bool DEV>
 struct Params<float, DEV> {
-  float k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw;
+  float k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw, g, iny2;
   __device__ explicit Params(const Coefs& c) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -122,8 +124,17 @@ struct Params<float, DEV> {
     rho0 = c.f_rho0;
     inv_rho0 = c.f_inv_rho0;
     uw = c.f_u_wall;
+    g = c.f_g_body;
+    iny2 = c.f_inv_ny2;
   }
 };
+
+template <typename CT>
+__device__ __forceinline__ CT sinpi_ct(CT x);
+template <>
+__device__ __forceinline__ float sinpi_ct<float>(float x) { return sinpif(x); }
+template <>
+__device__ __forceinline__ double sinpi_ct<double>(double x) { return sinpi(x); }
 
 template <typename CT>
 __device__ __forceinline__ CT rcp_ct(CT x);
@@ -357,8 +368,14 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
   // centre values (deviation records add the references back)
   const CT rho[2] = {DEV ? P.rref[0] + c0.ra : c0.ra, DEV ? P.rref[1] + c0.rb : c0.rb};
   const CT psi[2] = {DEV ? P.pref[0] + c0.pa : c0.pa, DEV ? P.pref[1] + c0.pb : c0.pb};
-  const CT F[2][2] = {{-psi[0] * Sxa - rho[0] * Xxa, -psi[0] * Sya - rho[0] * Xya},
-                      {-psi[1] * Sxb - rho[1] * Xxb, -psi[1] * Syb - rho[1] * Xyb}};
+  CT F[2][2] = {{-psi[0] * Sxa - rho[0] * Xxa, -psi[0] * Sya - rho[0] * Xya},
+                {-psi[1] * Sxb - rho[1] * Xxb, -psi[1] * Syb - rho[1] * Xyb}};
+  // shear forcing of Sec. VIII: rho_s g sin(2 pi y / ny) along x (row-uniform)
+  if (P.g != CT(0)) {
+    const CT gy = P.g * sinpi_ct<CT>((CT)y * P.iny2);
+    F[0][0] += rho[0] * gy;
+    F[1][0] += rho[1] * gy;
+  }
   // moments and the common velocity (Eq. (1) and the definition of u below it)
   CT jx[2], jy[2];
 #pragma unroll
@@ -404,6 +421,24 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
     for (int sp = 0; sp < 2; ++sp)
       pxy += ((double)f[sp][5] - (double)f[sp][6]) + ((double)f[sp][7] - (double)f[sp][8]);
     acc[6] += pxy;
+    // response mode (Sec. VIII, Eq. (68)): u_phys,x against sin(2 pi y / ny)
+    acc[7] += (jtx + 0.5 * Ftx) / rt * sinpi((double)y * (2.0 / (double)g.ny));
+    // interface indicator (Eq. (69)) with grad phi = 3 sum_{belt 1} w_i phi(r + c_i) c_i;
+    // the ring holds density deviations, whose differences are the densities'
+    double gax = 0, gay = 0, gbx = 0, gby = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int px = pair_cx(m), py = pair_cy(m);
+      const double w3 = pair_class(m) == 0 ? 3.0 / 9.0 : 3.0 / 36.0;
+      const Fld<CT>& hi = at(py, px);
+      const Fld<CT>& lo = at(-py, -px);
+      const double da = (double)hi.ra - (double)lo.ra, db = (double)hi.rb - (double)lo.rb;
+      gax += w3 * px * da;
+      gay += w3 * py * da;
+      gbx += w3 * px * db;
+      gby += w3 * py * db;
+    }
+    acc[8] -= gax * gbx + gay * gby;
     return;
   }
 

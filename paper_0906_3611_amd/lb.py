@@ -33,7 +33,8 @@ class lb_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("boundary", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("tau", ctypes.c_double * 2), ("rho0", ctypes.c_double),
                 ("G_a", ctypes.c_double * 2), ("G_r", ctypes.c_double * 2), ("G_AB", ctypes.c_double),
-                ("u_wall", ctypes.c_double), ("rho_ref", ctypes.c_double * 2),
+                ("u_wall", ctypes.c_double), ("body_force", ctypes.c_double),
+                ("rho_ref", ctypes.c_double * 2),
                 ("device_buffer", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t)]
 
 
@@ -41,7 +42,8 @@ class lb_obs(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("mass", ctypes.c_double * 2), ("mom", ctypes.c_double * 2),
                 ("mom_phys", ctypes.c_double * 2), ("pxy_kin", ctypes.c_double),
                 ("wall_stress", ctypes.c_double * 2), ("avg_count", ctypes.c_int64),
-                ("flags", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("flags", ctypes.c_int32), ("pad_", ctypes.c_int32), ("u_mode", ctypes.c_double),
+                ("i_ab", ctypes.c_double)]
 
 
 class lb_launch_info(ctypes.Structure):
@@ -165,7 +167,7 @@ def disc_fields(nx, ny, seed, phi, **kw):
 
 def make_params(nx, ny, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1),
                 G_AB=0.405, boundary="periodic", u_wall=0.0, precision="fp64",
-                rho_ref=(0.0, 0.0)) -> lb_params:
+                rho_ref=(0.0, 0.0), body_force=0.0) -> lb_params:
     """An lb_params record (parameters of Sec. II, Eqs. (1), (2), (5))."""
     p = lb_params()
     p.nx, p.ny = int(nx), int(ny)
@@ -177,15 +179,23 @@ def make_params(nx, ny, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1
     p.G_r[0], p.G_r[1] = G_r
     p.G_AB = G_AB
     p.u_wall = u_wall
+    p.body_force = body_force
     p.rho_ref[0], p.rho_ref[1] = rho_ref
     return p
+
+
+def kolmogorov_force(U0, ny, tau=1.0):
+    """Body-force amplitude g that drives U_x = U0 sin(2 pi y / ny) in a
+    fluid of kinematic viscosity nu = (tau - 1/2)/3 (Sec. VIII): g = nu k^2 U0."""
+    k = 2.0 * np.pi / ny
+    return (tau - 0.5) / 3.0 * k * k * U0
 
 
 def _obs_dict(o) -> dict:
     return {"step": o.step, "mass": np.array(o.mass[:]), "mom": np.array(o.mom[:]),
             "mom_phys": np.array(o.mom_phys[:]), "pxy_kin": o.pxy_kin,
             "wall_stress": np.array(o.wall_stress[:]), "avg_count": o.avg_count,
-            "flags": o.flags}
+            "flags": o.flags, "u_mode": o.u_mode, "i_ab": o.i_ab}
 
 
 def _info_dict(li) -> dict:
@@ -241,12 +251,12 @@ class Lattice(_Handle):
 
     def __init__(self, nx: int, ny: int, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0),
                  G_r=(8.1, 8.1), G_AB=0.405, boundary="periodic", u_wall=0.0, precision="fp64",
-                 rho_ref=(0.0, 0.0), use_torch=True, stream=None):
+                 rho_ref=(0.0, 0.0), body_force=0.0, use_torch=True, stream=None):
         self._lib = load()
         self._h = ctypes.c_void_p()
         self.nx, self.ny = int(nx), int(ny)
         p = make_params(nx, ny, tau=tau, rho0=rho0, G_a=G_a, G_r=G_r, G_AB=G_AB, boundary=boundary,
-                        u_wall=u_wall, precision=precision, rho_ref=rho_ref)
+                        u_wall=u_wall, precision=precision, rho_ref=rho_ref, body_force=body_force)
         self.precision, self.boundary = precision, boundary
         nbytes = ctypes.c_size_t()
         self._check(self._lib.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)), "workspace")

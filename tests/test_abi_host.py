@@ -21,7 +21,7 @@ def test_every_declared_function_is_exported(L):
     assert len(names) >= 17
     for n in names:
         assert hasattr(L, n), n
-    assert L.lb_abi_version() == 1
+    assert L.lb_abi_version() == 2
 
 
 def _params(**kw):

@@ -311,3 +311,61 @@ def test_invalid_init_rejected():
     with pytest.raises(lb.LBError) as ei:
         lat.step(1)
     assert ei.value.code == lb.LB_E_STATE
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+@pytest.mark.parametrize("boundary", ["periodic", "couette"])
+def test_shear_forcing_and_response_observables(precision, boundary):
+    """Sec. VIII: body force rho_s g sin(2 pi y / ny) on the standard rho0 = 0.7
+    couplings; fields, the response mode u_mode (Eq. (68)) and the interface
+    indicator i_ab (Eq. (69)) against the oracle.  These couplings amplify
+    rounding ~1e4-fold in 150 steps, so the tolerance is max(floor, 100 x the
+    oracle's own twin envelope): the oracle rerun from the initial fields
+    perturbed by one ulp of the storage precision (FP64), or rounded to FP32
+    (FP32 deviation storage, checked over the first 30 steps)."""
+    par = dict(tau=(1.0, 1.0), rho0=0.7, G_a=(-15.0, -14.0), G_r=(14.1, 13.1), G_AB=0.405)
+    nx, ny, g = 64, 48, 2e-4
+    u_wall = 0.01 if boundary == "couette" else 0.0
+    lat = _lb().Lattice(nx, ny, precision=precision, boundary=boundary, u_wall=u_wall,
+                        body_force=g, **par)
+    p = oparams(nx, ny, boundary=boundary, u_wall=u_wall, **par)
+    p.g_body = g
+    ra, rb = inputs.noise_fields(nx, ny, 8, 0.612, 0.612, 0.01)
+    lat.init(ra, rb)
+    f = oracle.init_equilibrium(p, ra, rb)
+    if precision == "fp64":
+        twin_ra, floor, checkpoints = np.nextafter(ra, 2.0), 1e-13, (1, 30, 150)
+    else:
+        twin_ra, floor, checkpoints = ra.astype(np.float32).astype(np.float64), 2e-6, (1, 10, 30)
+    ft = oracle.init_equilibrium(p, twin_ra, rb)
+    done = 0
+    for k in checkpoints:
+        lat.step(k - done)
+        f, _ = oracle.run(p, f, k - done)
+        ft, _ = oracle.run(p, ft, k - done)
+        done = k
+        fl, ref, twin = lat.fields(), oracle.fields(p, f), oracle.fields(p, ft)
+        for key in ("rho", "uphys"):
+            env = np.abs(twin[key] - ref[key]).max()
+            err = np.abs(fl[key] - ref[key]).max()
+            assert err < max(floor, 100 * env), (k, key, err, env)
+        o, t, tt = lat.observables(), oracle.totals(p, f), oracle.totals(p, ft)
+        for key, fl_rel in (("u_mode", 1e-10), ("i_ab", 1e-10)):
+            env = abs(tt[key] - t[key])
+            fl_abs = (fl_rel if precision == "fp64" else 1e-4) * abs(t[key])
+            assert abs(o[key] - t[key]) < max(fl_abs, 100 * env) + 1e-15, (k, key, o[key], t[key], env)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-8), ("fp32dev", 2e-3)])
+def test_kolmogorov_flow_exact_at_tau_one_on_gpu(precision, tol):
+    """Non-interacting mixture at tau = 1 driven by g sin(k y): the steady
+    first mode is g (1/a - 1/2), a = (1 - cos k)/3, exactly on the lattice."""
+    import math
+    nx, ny, g = 64, 64, 1e-6
+    lat = _lb().Lattice(nx, ny, precision=precision, tau=(1.0, 1.0), rho0=1.0, G_a=(0, 0),
+                        G_r=(0, 0), G_AB=0.0, body_force=g)
+    lat.init(np.full((ny, nx), 0.6), np.full((ny, nx), 0.4))
+    lat.step(15000)
+    k = 2.0 * math.pi / ny
+    a = (1.0 - math.cos(k)) / 3.0
+    assert lat.observables()["u_mode"] == pytest.approx(g * (1.0 / a - 0.5), rel=tol)
