@@ -34,9 +34,18 @@ KERNEL_SRC = os.path.join(ROOT, "paper_0906_3611_amd", "csrc", "lb_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 
 
+def code_hash(text: str) -> str:
+    """sha256 (16 hex) of C++ source with comments and whitespace removed, so
+    that edits of comments alone keep measurements valid."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256("".join(text.split()).encode()).hexdigest()[:16]
+
+
 def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    with open(KERNEL_SRC) as fh:
+        return code_hash(fh.read())
 
 
 def ensure_built():
@@ -170,7 +179,7 @@ def bench_kolmogorov(speeds=(0.005, 0.01, 0.02, 0.03, 0.04, 0.05), n=128,
     standard rho0 = 0.7 couplings, <rho_A> = <rho_B> = 0.612 +- 0.01, tau = 1,
     body force driving U_x = U0 sin(2 pi y / n), one lattice per U0 in one
     batch (graph replay, autotuned).  Reports the response R = u_mode / U0
-    (Eq. (68)) and the interface indicator I_AB (Eq. (69)) at each checkpoint."""
+    (Eq. (66)) and the interface indicator I_AB (Eq. (67)) at each checkpoint."""
     from paper_0906_3611_amd import inputs, lb
     par = dict(tau=(1.0, 1.0), rho0=0.7, G_a=(-15.0, -14.0), G_r=(14.1, 13.1), G_AB=0.405)
     specs = [dict(par, nx=n, ny=n, precision="fp32dev", body_force=lb.kolmogorov_force(U, n))

@@ -100,9 +100,9 @@ typedef struct {
   double u_mode;         /* first sine mode of the line-averaged x-velocity,
                             (2 / (nx ny)) sum_r u_phys,x sin(2 pi y / ny);
                             divided by U0 it is the response R(t) of
-                            Sec. VIII, Eq. (68) */
+                            Sec. VIII, Eq. (66) */
   double i_ab;           /* interface indicator -sum_r grad rho_A . grad rho_B
-                            (Sec. VIII, Eq. (69)); grad phi = (1 / c_s^2)
+                            (Sec. VIII, Eq. (67)); grad phi = (1 / c_s^2)
                             sum_{i=1..8} w_i phi(r + c_i) c_i over the force
                             stencil's neighbours (mirrored at walls) */
 } lb_obs;

@@ -175,7 +175,7 @@ def fields(p: Params, f: np.ndarray) -> dict:
 def totals(p: Params, f: np.ndarray) -> dict:
     """Global sums of the state: mass[2], mom[2], mom_phys[2], pxy_kin, the
     first sine mode u_mode of the line-averaged x-velocity (R(t) times U0,
-    Sec. VIII Eq. (68)) and the interface indicator i_ab (Eq. (69))."""
+    Sec. VIII Eq. (66)) and the interface indicator i_ab (Eq. (67))."""
     f = _f64(f)
     out = np.zeros(9)
     cp = p.c()

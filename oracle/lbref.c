@@ -387,10 +387,10 @@ int lbref_fields(const lbref_params* p, const double* f, double* rho, double* u,
  *   out[4..5] total momentum with half the force, sum_r (sum_s j_s + F/2),
  *   out[6]    kinetic stress sum_r sum_s sum_i f_is c_ix c_iy (Sec. III, Eq. (10)),
  *   out[7]    first sine mode of the line-averaged x-velocity (Sec. VIII,
- *             Eq. (68)): (2 / ny) sum_y sin(2 pi y / ny) Ubar(y), Ubar(y) =
+ *             Eq. (66)): (2 / ny) sum_y sin(2 pi y / ny) Ubar(y), Ubar(y) =
  *             sum_x uphys_x / nx; divided by U0 it is the response R(t),
  *   out[8]    interface indicator I_AB = - sum_r grad rho_A . grad rho_B
- *             (Sec. VIII, Eq. (69)), with the lattice gradient
+ *             (Sec. VIII, Eq. (67)), with the lattice gradient
  *             grad phi(r) = (1 / c_s^2) sum_{i=1..8} w_i phi(r + c_i) c_i over
  *             the force stencil's neighbours (wrapped, or mirrored at walls). */
 int lbref_totals(const lbref_params* p, const double* f, double* out) {

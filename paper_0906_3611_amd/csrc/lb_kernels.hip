@@ -421,9 +421,9 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
     for (int sp = 0; sp < 2; ++sp)
       pxy += ((double)f[sp][5] - (double)f[sp][6]) + ((double)f[sp][7] - (double)f[sp][8]);
     acc[6] += pxy;
-    // response mode (Sec. VIII, Eq. (68)): u_phys,x against sin(2 pi y / ny)
+    // response mode (Sec. VIII, Eq. (66)): u_phys,x against sin(2 pi y / ny)
     acc[7] += (jtx + 0.5 * Ftx) / rt * sinpi((double)y * (2.0 / (double)g.ny));
-    // interface indicator (Eq. (69)) with grad phi = 3 sum_{belt 1} w_i phi(r + c_i) c_i;
+    // interface indicator (Eq. (67)) with grad phi = 3 sum_{belt 1} w_i phi(r + c_i) c_i;
     // the ring holds density deviations, whose differences are the densities'
     double gax = 0, gay = 0, gbx = 0, gby = 0;
 #pragma unroll

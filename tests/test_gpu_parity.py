@@ -317,8 +317,8 @@ def test_invalid_init_rejected():
 @pytest.mark.parametrize("boundary", ["periodic", "couette"])
 def test_shear_forcing_and_response_observables(precision, boundary):
     """Sec. VIII: body force rho_s g sin(2 pi y / ny) on the standard rho0 = 0.7
-    couplings; fields, the response mode u_mode (Eq. (68)) and the interface
-    indicator i_ab (Eq. (69)) against the oracle.  These couplings amplify
+    couplings; fields, the response mode u_mode (Eq. (66)) and the interface
+    indicator i_ab (Eq. (67)) against the oracle.  These couplings amplify
     rounding ~1e4-fold in 150 steps, so the tolerance is max(floor, 100 x the
     oracle's own twin envelope): the oracle rerun from the initial fields
     perturbed by one ulp of the storage precision (FP64), or rounded to FP32

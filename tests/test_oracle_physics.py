@@ -14,7 +14,7 @@
   the bulk-pressure jump across a circular interface falls as 1/R.
 * Shear forcing of Sec. VIII: the steady Kolmogorov flow of a non-interacting
   mixture (exact on the lattice at tau = 1, second order in k otherwise),
-  its first-mode response (Eq. (68)), and the interface indicator (Eq. (69))
+  its first-mode response (Eq. (66)), and the interface indicator (Eq. (67))
   of a sine profile.
 """
 import math
