@@ -205,6 +205,47 @@ def bench_kolmogorov(speeds=(0.005, 0.01, 0.02, 0.03, 0.04, 0.05), n=128,
             "U0": list(speeds), "checkpoints": rows}
 
 
+def bench_ensemble(n_real=100, n=128, U0=0.02, steps=100000, every=10000, t_w=20000, seed0=100):
+    """Ensemble observables of Secs. VIII-IX on the batch engine: n_real
+    realizations (noise seeds seed0 + i) of the 128^2 shear problem with the
+    rho0 = 0.7 standard set, all in one batch.  Reports, every `every` steps,
+    the mean and kurtosis of R(t) over realizations (Fig. 16), and the ageing
+    overlap C(t_w, dt_w) of Eq. (68) for t_w = 20000 (Fig. 12).  The paper runs
+    10^6 steps; this is the first 10^5."""
+    import numpy as np
+    from paper_0906_3611_amd import analysis, inputs, lb
+    par = dict(tau=(1.0, 1.0), rho0=0.7, G_a=(-15.0, -14.0), G_r=(14.1, 13.1), G_AB=0.405)
+    g = lb.kolmogorov_force(U0, n)
+    b = lb.Batch([dict(par, nx=n, ny=n, precision="fp32dev", body_force=g)] * n_real)
+    for i in range(n_real):
+        ra, rb = inputs.noise_fields(n, n, seed0 + i, 0.612, 0.612, 0.01)
+        b.init(i, ra, rb)
+    b.set_launch(use_graph=1)
+    b.autotune(steps=20)
+
+    def phi_all():
+        return np.stack([analysis.order_parameter(b.fields(i)["rho"]) for i in range(n_real)])
+
+    rows, overlaps, done, ms, phi_w = [], [], 0, 0.0, None
+    for t in range(every, steps + 1, every):
+        if phi_w is None and t > t_w:
+            ms += _timed(b.stream, lambda: b.step(t_w - done))
+            done = t_w
+            phi_w = phi_all()
+        ms += _timed(b.stream, lambda: b.step(t - done))
+        done = t
+        R = analysis.response([o["u_mode"] for o in b.observables()], U0)
+        rows.append({"t": t, "R_mean": float(R.mean()), "R_std": float(R.std()),
+                     "kurtosis": analysis.kurtosis(R)})
+        if phi_w is not None:
+            overlaps.append({"dt_w": t - t_w, "C": analysis.overlap(phi_w, phi_all())})
+    b.close()
+    return {"workload": f"{n_real} realizations {n}x{n} (seeds {seed0}..{seed0 + n_real - 1}), rho0 = 0.7 "
+                        f"standard set, <rho> = 0.612 +- 0.01, U0 = {U0}, fp32dev, {steps} steps, one batch",
+            "value": n_real * n * n * done / (ms * 1e-3) / 1e6, "R": rows, "overlap_t_w": t_w,
+            "overlap": overlaps}
+
+
 def bench_batch(n=256, steps=5000, seed=4, tune_steps=10):
     """Ensemble of n independent square lattices (sides log-uniform in
     [128, 1024], G^a in [-9.5, -8.5], disc fraction in [0.5, 0.8]) in FP32
@@ -472,6 +513,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 1 GiB copy")
     ap.add_argument("--no-couette", action="store_true", help="skip the Couette channel runs")
     ap.add_argument("--no-kolmogorov", action="store_true", help="skip the shear-forcing protocol")
+    ap.add_argument("--no-ensemble", action="store_true", help="skip the 100-realization ensemble")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--ensemble", type=int, default=256, help="lattices in the batched ensemble")
@@ -533,6 +575,10 @@ def main():
     if not args.no_kolmogorov:
         extra["kolmogorov"] = bench_kolmogorov()
         print(f"# kolmogorov batch: {extra['kolmogorov']['value']:.0f} MLUPS", file=sys.stderr,
+              flush=True)
+    if not args.no_ensemble:
+        extra["shear_ensemble"] = bench_ensemble()
+        print(f"# shear ensemble: {extra['shear_ensemble']['value']:.0f} MLUPS", file=sys.stderr,
               flush=True)
     if not args.no_batch:
         extra["batched_ensemble"] = bench_batch(args.ensemble, args.ensemble_steps)
