@@ -56,6 +56,14 @@ struct Fld {
   CT pa, pb, ra, rb;  // psi_A, psi_B, rho_A, rho_B
 };
 
+// One LDS ring entry of one field for both species.  psi and rho live in
+// separate planes, so the 24 psi reads and the 8 rho reads of a site are
+// unit-stride across the wave (no bank conflicts, no unused bytes).
+template <typename CT>
+struct Pr {
+  CT a, b;
+};
+
 template <typename CT>
 __device__ __forceinline__ CT exp_ct(CT x);
 template <>
@@ -311,9 +319,6 @@ __host__ __device__ constexpr int pair_class(int m) {
 
 // Collide the sites of lattice row y whose stencil rows sit in LDS ring
 // slots slot[0..4] (dy = -2..2).  Lane l owns LDS column l + 2.
-#ifndef LDS_GROUP
-#define LDS_GROUP 0
-#endif
 // Per-wave output context of a collision.
 template <typename ST>
 struct Out {
@@ -326,24 +331,24 @@ struct Out {
 
 template <typename CT, bool DEV, bool WALLS, int MODE, typename ST, bool NT>
 __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, DEV>& P,
-                                            const Fld<CT>* __restrict__ ring, int lc,
+                                            const Pr<CT>* __restrict__ ring_p,
+                                            const Pr<CT>* __restrict__ ring_r, int lc,
                                             const int (&slot)[5], int y, int col, uint32_t ob_c,
                                             const CT (&f)[2][9], double (&acc)[kNRed],
                                             double (&wacc)[2], bool& bad) {
   const Geometry& g = a.g;
   constexpr int W = kWave + 4;
-  auto at = [&](int dy, int dx) -> const Fld<CT>& { return ring[slot[dy + 2] * W + lc + dx]; };
+  auto atp = [&](int dy, int dx) -> const Pr<CT>& { return ring_p[slot[dy + 2] * W + lc + dx]; };
+  auto atr = [&](int dy, int dx) -> const Pr<CT>& { return ring_r[slot[dy + 2] * W + lc + dx]; };
   // Shan-Chen sums over +-c pairs (Eq. (2)): S_s = sum_i k_s(i) psi_s(r + c_i) c_i,
   // X_s = sum_{belt 1} (G_AB / rho0^2) w_i rho_other(r + c_i) c_i.
   CT Sxa = 0, Sya = 0, Sxb = 0, Syb = 0, Xxa = 0, Xya = 0, Xxb = 0, Xyb = 0;
 #pragma unroll
   for (int m = 0; m < 12; ++m) {
-    // keep the LDS reads of a few pairs in flight at a time, not all 25
-    if (LDS_GROUP > 0 && m % LDS_GROUP == 0) __builtin_amdgcn_sched_barrier(0);
     const int px = pair_cx(m), py = pair_cy(m), k = pair_class(m);
-    const Fld<CT>& hi = at(py, px);
-    const Fld<CT>& lo = at(-py, -px);
-    const CT da = hi.pa - lo.pa, db = hi.pb - lo.pb;
+    const Pr<CT>& hi = atp(py, px);
+    const Pr<CT>& lo = atp(-py, -px);
+    const CT da = hi.a - lo.a, db = hi.b - lo.b;
     if (px) {
       Sxa += (P.k[0][k] * (CT)px) * da;
       Sxb += (P.k[1][k] * (CT)px) * db;
@@ -353,7 +358,9 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
       Syb += (P.k[1][k] * (CT)py) * db;
     }
     if (m < 4) {
-      const CT ea = hi.ra - lo.ra, eb = hi.rb - lo.rb;  // A's density acts on B and back
+      const Pr<CT>& rhi = atr(py, px);
+      const Pr<CT>& rlo = atr(-py, -px);
+      const CT ea = rhi.a - rlo.a, eb = rhi.b - rlo.b;  // A's density acts on B and back
       if (px) {
         Xxa += (P.kx[k] * (CT)px) * eb;
         Xxb += (P.kx[k] * (CT)px) * ea;
@@ -364,10 +371,10 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
       }
     }
   }
-  const Fld<CT> c0 = at(0, 0);
+  const Pr<CT> c0p = atp(0, 0), c0r = atr(0, 0);
   // centre values (deviation records add the references back)
-  const CT rho[2] = {DEV ? P.rref[0] + c0.ra : c0.ra, DEV ? P.rref[1] + c0.rb : c0.rb};
-  const CT psi[2] = {DEV ? P.pref[0] + c0.pa : c0.pa, DEV ? P.pref[1] + c0.pb : c0.pb};
+  const CT rho[2] = {DEV ? P.rref[0] + c0r.a : c0r.a, DEV ? P.rref[1] + c0r.b : c0r.b};
+  const CT psi[2] = {DEV ? P.pref[0] + c0p.a : c0p.a, DEV ? P.pref[1] + c0p.b : c0p.b};
   CT F[2][2] = {{-psi[0] * Sxa - rho[0] * Xxa, -psi[0] * Sya - rho[0] * Xya},
                 {-psi[1] * Sxb - rho[1] * Xxb, -psi[1] * Syb - rho[1] * Xyb}};
   // shear forcing of Sec. VIII: rho_s g sin(2 pi y / ny) along x (row-uniform)
@@ -430,9 +437,9 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
     for (int m = 0; m < 4; ++m) {
       const int px = pair_cx(m), py = pair_cy(m);
       const double w3 = pair_class(m) == 0 ? 3.0 / 9.0 : 3.0 / 36.0;
-      const Fld<CT>& hi = at(py, px);
-      const Fld<CT>& lo = at(-py, -px);
-      const double da = (double)hi.ra - (double)lo.ra, db = (double)hi.rb - (double)lo.rb;
+      const Pr<CT>& hi = atr(py, px);
+      const Pr<CT>& lo = atr(-py, -px);
+      const double da = (double)hi.a - (double)lo.a, db = (double)hi.b - (double)lo.b;
       gax += w3 * px * da;
       gay += w3 * py * da;
       gbx += w3 * px * db;
@@ -453,7 +460,7 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
     const CT vx = ux + P.tau[sp] * F[sp][0] * ir;
     const CT vy = uy + P.tau[sp] * F[sp][1] * ir;
     const CT usq = CT(1.5) * (vx * vx + vy * vy);
-    const CT drho = DEV ? (sp == 0 ? c0.ra : c0.rb) : CT(0);  // sum of the deviations
+    const CT drho = DEV ? (sp == 0 ? c0r.a : c0r.b) : CT(0);  // sum of the deviations
     CT post[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -507,7 +514,8 @@ template <typename ST, typename CT, bool DEV, bool WALLS, int MODE, int PF, bool
 __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
   constexpr int W = kWave + 4;
   constexpr int NSET = 3 + PF;
-  __shared__ Fld<CT> ring[kRing * W];
+  __shared__ Pr<CT> ring_p[kRing * W];  // psi of the 5 stencil rows
+  __shared__ Pr<CT> ring_r[kRing * W];  // rho of the 5 stencil rows
   __shared__ CT rstage[72];  // pulled ring-column values of the current row
   const int b = blockIdx.x;
   const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
@@ -586,19 +594,23 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
       rstage[lane] = (CT)ri[j][0];
       if (lane < 8) rstage[kWave + lane] = (CT)ri[j][1];
       lds_fence();
-      Fld<CT>* row = ring + (k % kRing) * W;
-      if (active) row[lane + 2] = fl;
+      Pr<CT>* rowp = ring_p + (k % kRing) * W;
+      Pr<CT>* rowr = ring_r + (k % kRing) * W;
+      if (active) {
+        rowp[lane + 2] = Pr<CT>{fl.pa, fl.pb};
+        rowr[lane + 2] = Pr<CT>{fl.ra, fl.rb};
+      }
       if (lane < 8) {
         CT acc = rstage[(rsp * 9) * 4 + rcl];
 #pragma unroll
         for (int i = 1; i < 9; ++i) acc += rstage[(rsp * 9 + i) * 4 + rcl];
         const CT ps = psi_of<CT, DEV>(P, rsp, acc);
         if (rsp) {
-          row[rpos].pb = ps;
-          row[rpos].rb = acc;
+          rowp[rpos].b = ps;
+          rowr[rpos].b = acc;
         } else {
-          row[rpos].pa = ps;
-          row[rpos].ra = acc;
+          rowp[rpos].a = ps;
+          rowr[rpos].a = acc;
         }
       }
       lds_fence();
@@ -608,7 +620,7 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
 #pragma unroll
         for (int d = 0; d < 5; ++d) slot[d] = (k - 2 + dir * (d - 2)) % kRing;
         const int y = lattice_row(k - 2);
-        collide_row<CT, DEV, WALLS, MODE, ST, NT>(out, P, ring, lane + 2, slot, y, col, ob_c,
+        collide_row<CT, DEV, WALLS, MODE, ST, NT>(out, P, ring_p, ring_r, lane + 2, slot, y, col, ob_c,
                                               fr[(j + NSET - 2) % NSET], acc, wacc, bad);
       }
       if (MODE == kObserve && k >= 4) {
