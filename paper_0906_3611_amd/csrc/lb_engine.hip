@@ -25,10 +25,15 @@ constexpr size_t kInfinityCacheBytes = 256ull << 20;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
-// Tiles: 64-column strips x row segments.  Segments of 32 rows (4 ring
-// rows re-read per 32), shorter ones (down to 8 rows) where that leaves
-// fewer than about 2048 wavefronts (8 per CU) to keep HBM busy.
-// seg_h > 0 forces the segment height.
+// Default tile policy (measured): FP32 kernels fit 2-3 waves per SIMD, FP64
+// ones 1, so FP32 aims at ~2048 wavefronts with 32-row segments and FP64 at
+// ~1024 with 64-row segments; segments get shorter (down to 8 rows) only to
+// reach that many tiles.
+int target_tiles(const lb_params* p) { return p->precision == LB_FP64 ? 1024 : 2048; }
+int base_seg_h(const lb_params* p) { return p->precision == LB_FP64 ? 64 : 32; }
+
+// Tiles: 64-column strips x row segments (see target_tiles).  seg_h > 0
+// forces the segment height.
 lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   lbk::Geometry g{};
   g.nx = p->nx;
@@ -36,7 +41,8 @@ lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   g.pitch = (p->nx + lbk::kWave - 1) / lbk::kWave * lbk::kWave;  // strips start on a line
   g.row_elems = (long long)(g.pitch / lbk::kWave) * 18 * lbk::kWave;
   g.nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
-  int nsegs = std::max((p->ny + 31) / 32, (2048 + g.nstrips - 1) / g.nstrips);
+  const int h0 = base_seg_h(p);
+  int nsegs = std::max((p->ny + h0 - 1) / h0, (target_tiles(p) + g.nstrips - 1) / g.nstrips);
   nsegs = std::min(nsegs, std::max(1, p->ny / 8));
   if (seg_h <= 0) {
     if (const char* e = std::getenv("LBSOFT_SEG_H")) seg_h = std::atoi(e);
@@ -218,17 +224,18 @@ void choose_default_variant(Engine& E);
 
 // Member geometries.  A forced height applies to every member.  Otherwise a
 // single lattice uses make_geometry's policy, and several lattices share one
-// segment height: 32 rows, halved (down to 8) only while the engine's tiles
-// stay under about 2048, so that small members are not cut into 8-row
-// segments when the whole launch has tiles to spare.
+// segment height: base_seg_h, halved (down to 8) only while the engine's
+// tiles stay under target_tiles, so that small members are not cut into
+// 8-row segments when the whole launch has tiles to spare.
 std::vector<lbk::Geometry> geometries(const Engine& E, int seg_h) {
   std::vector<lbk::Geometry> g;
   int h = seg_h;
   if (seg_h < 4 && E.m.size() > 1) {
-    for (h = 32; h > 8; h /= 2) {
+    const lb_params* p0 = &E.m[0].p;  // members share the precision
+    for (h = base_seg_h(p0); h > 8; h /= 2) {
       long long tiles = 0;
       for (auto& mm : E.m) tiles += (long long)make_geometry(&mm.p, h).ntiles;
-      if (tiles >= 2048) break;
+      if (tiles >= target_tiles(p0)) break;
     }
   }
   for (auto& mm : E.m) g.push_back(make_geometry(&mm.p, h));
@@ -264,14 +271,15 @@ int retile(Engine& E) {
 }
 
 void choose_default_variant(Engine& E) {
-  // Defaults (measured): when the population buffers exceed the 256 MB
-  // Infinity Cache, streaming stores and no prefetch (three FP32 waves per
-  // SIMD); when they fit, cached stores and a one-row prefetch for FP32.
+  // Defaults (measured): streaming stores when the population buffers
+  // exceed the 256 MB Infinity Cache.  FP32: no prefetch then (three waves
+  // per SIMD), a one-row prefetch when they fit.  FP64 (one wave per SIMD):
+  // always a one-row prefetch.
   if (E.variant_forced) return;
   size_t total_pop = 0;
   for (auto& mm : E.m) total_pop += 2 * mm.pop_bytes;
   const bool hbm = total_pop > kInfinityCacheBytes;
-  E.variant.prefetch = (E.fp64 || hbm) ? 0 : 1;
+  E.variant.prefetch = (E.fp64 || !hbm) ? 1 : 0;
   E.variant.stream_stores = hbm ? 1 : 0;
   if (const char* e = std::getenv("LBSOFT_PREFETCH"))
     E.variant.prefetch = std::max(0, std::min(std::atoi(e), 2));
