@@ -88,22 +88,43 @@ def run_gpu(nx, ny, precision, steps, warmup, rho_a, rho_b):
             "rho": rho}
 
 
-def cpu_baseline(nx, ny, rho_a, rho_b, budget_s=15.0):
-    """The FP64 oracle on the host cores, on a bounded number of steps."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, p, f, budget_s, max_steps):
+    t0 = time.perf_counter()
+    f, _ = oracle.run(p, f, 1)
+    t1 = time.perf_counter() - t0
+    n = max(1, min(max_steps, int(budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.run(p, f, n)
+    dt = time.perf_counter() - t0
+    return p.nx * p.ny * n / dt / 1e6, n, dt
+
+
+def cpu_baseline(nx, ny, rho_a, rho_b, budget_s=10.0):
+    """The FP64 oracle on the host cores (all OpenMP threads, then one), on a
+    bounded number of steps of the same workload."""
     import oracle
     p = oracle.Params(nx=nx, ny=ny, tau=PARAMS["tau"], rho0=PARAMS["rho0"], Ga=PARAMS["G_a"],
                       Gr=PARAMS["G_r"], Gab=PARAMS["G_AB"])
     f = oracle.init_equilibrium(p, rho_a, rho_b)
-    t0 = time.perf_counter()
-    f, _ = oracle.run(p, f, 1)
-    t1 = time.perf_counter() - t0
-    n = max(1, min(60, int(budget_s / max(t1, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.run(p, f, n)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": nx * ny * n / dt / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{nx}x{ny} disc emulsion, FP64, {n} steps after 1 untimed, {dt:.1f} s"}
+    cores = oracle.max_threads()
+    v, n, dt = _oracle_rate(oracle, p, f, budget_s, 60)
+    oracle.set_threads(1)
+    v1, n1, dt1 = _oracle_rate(oracle, p, f, budget_s / 2, 10)
+    oracle.set_threads(cores)
+    return {"value": v, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{nx}x{ny} disc emulsion, FP64, {n} steps after 1 untimed, {dt:.1f} s",
+            "value_1_thread": v1, "sample_1_thread": f"{n1} steps, {dt1:.1f} s",
+            "cpu": _cpu_model(), "nproc": os.cpu_count()}
 
 
 def _timed(stream, fn):
@@ -569,6 +590,13 @@ def main():
                                         "achieved_gbs": pr["achieved_gbs"],
                                         "frac": pr["achieved_gbs"] / PEAK_HBM_GBS}
         print(f"# probe 4096x1024: {pr['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        # 4096^2 (2.4 GB of FP32 populations)
+        qa, qb = inputs.noise_fields(4096, 4096, 3, 0.5, 0.5, 0.01)
+        pq = run_gpu(4096, 4096, args.precision, 400, 20, qa, qb)
+        extra["hbm_probe_4096x4096"] = {"value": pq["mlups"], "ms_per_step": pq["ms_per_step"],
+                                        "achieved_gbs": pq["achieved_gbs"],
+                                        "frac": pq["achieved_gbs"] / PEAK_HBM_GBS}
+        print(f"# probe 4096x4096: {pq['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
     if not args.no_couette:
         extra["couette"] = bench_couette()

@@ -102,6 +102,10 @@ def lib():
         L.lbref_work_doubles.restype = ctypes.c_size_t
         ip = ctypes.POINTER(ctypes.c_int)
         L.lbref_tables.argtypes = [ip, ip, dp, ip, ip, dp, dp]
+        L.lbref_max_threads.argtypes = []
+        L.lbref_max_threads.restype = ctypes.c_int
+        L.lbref_set_threads.argtypes = [ctypes.c_int]
+        L.lbref_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -219,3 +223,13 @@ def tables() -> dict:
     lib().lbref_tables(ci, cyi, wq, ex, ey, pe, we)
     return {"cx": list(ci), "cy": list(cyi), "wq": list(wq), "ex": list(ex), "ey": list(ey),
             "p": list(pe), "w": list(we)}
+
+
+def max_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().lbref_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the oracle's OpenMP thread count (n > 0)."""
+    lib().lbref_set_threads(int(n))

@@ -18,6 +18,9 @@
  * f holds the pre-collision populations at integer time t.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -462,3 +465,19 @@ void lbref_tables(int* cx, int* cy, double* wq, int* ex, int* ey, double* pe, do
 }
 
 int lbref_abi_version(void) { return 1; }
+
+/* Threads of the OpenMP loops (for timing the oracle as a baseline). */
+int lbref_max_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+void lbref_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
