@@ -194,6 +194,43 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
                               "points": curve}}
 
 
+def bench_precision(nx, ny, rho_a, rho_b, checkpoints=(1000, 5000, 10000, 20000)):
+    """FP32-deviation storage against FP64 storage on the full workload: max
+    |delta rho| and |delta u_phys| at each checkpoint, next to the FP64 twin
+    envelope (the same FP64 run started from rho_A perturbed by one ulp) and
+    an FP32-rounding twin (FP64 started from rho_A rounded to FP32)."""
+    import numpy as np
+    from paper_0906_3611_amd import lb
+    runs = {}
+    starts = {"fp64": (rho_a, "fp64"), "fp32dev": (rho_a, "fp32dev"),
+              "twin_ulp": (np.nextafter(rho_a, 2.0), "fp64"),
+              "twin_f32": (rho_a.astype(np.float32).astype(np.float64), "fp64")}
+    for name, (ra, prec) in starts.items():
+        lat = lb.Lattice(nx, ny, precision=prec, **PARAMS)
+        lat.init(ra, rho_b)
+        out, done = [], 0
+        for t in checkpoints:
+            lat.step(t - done)
+            done = t
+            fl, o = lat.fields(), lat.observables()
+            out.append((fl["rho"], fl["uphys"], o))
+        lat.close()
+        runs[name] = out
+    rows = []
+    for k, t in enumerate(checkpoints):
+        ref_r, ref_u, ref_o = runs["fp64"][k]
+        row = {"t": t}
+        for name in ("fp32dev", "twin_ulp", "twin_f32"):
+            r, u, o = runs[name][k]
+            row[name] = {"rho": float(np.abs(r - ref_r).max()), "u": float(np.abs(u - ref_u).max()),
+                         "mass_rel": float(np.abs(o["mass"] / ref_o["mass"] - 1).max()),
+                         "i_ab_rel": float(abs(o["i_ab"] / ref_o["i_ab"] - 1)),
+                         "mean_speed_rel": float(np.mean(np.hypot(*u)) / np.mean(np.hypot(*ref_u)) - 1)}
+        rows.append(row)
+    return {"workload": f"{nx}x{ny} disc emulsion as the headline run; GPU FP64 as reference",
+            "rows": rows}
+
+
 def bench_kolmogorov(speeds=(0.005, 0.01, 0.02, 0.03, 0.04, 0.05), n=128,
                      checkpoints=(1000, 10000, 100000), seed=10):
     """The shear protocol of Sec. VIII (Figs. 10, 11): 128^2 periodic, the
@@ -534,6 +571,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 1 GiB copy")
     ap.add_argument("--no-couette", action="store_true", help="skip the Couette channel runs")
     ap.add_argument("--no-kolmogorov", action="store_true", help="skip the shear-forcing protocol")
+    ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 error study")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 100-realization ensemble")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
@@ -598,6 +636,9 @@ def main():
                                         "frac": pq["achieved_gbs"] / PEAK_HBM_GBS}
         print(f"# probe 4096x4096: {pq['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
+    if not args.no_precision and (nx, ny) == (1024, 1024):
+        extra["precision_c2"] = bench_precision(nx, ny, rho_a, rho_b)
+        print("# precision study done", file=sys.stderr, flush=True)
     if not args.no_couette:
         extra["couette"] = bench_couette()
     if not args.no_kolmogorov:
