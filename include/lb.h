@@ -52,7 +52,7 @@ enum {
 };
 
 enum { LB_PERIODIC = 0, LB_COUETTE_Y = 1 };
-enum { LB_FP64 = 0, LB_FP32_DEV = 1 };
+enum { LB_FP64 = 0, LB_FP32_DEV = 1, LB_FP32_MOM = 2 };
 
 /* Model and storage parameters.  Constraints checked by lb_create():
  * nx, ny >= 5 (the +-2 stencil must reach distinct sites); tau_s > 1/2;
@@ -63,7 +63,15 @@ typedef struct {
   int32_t boundary;   /* LB_PERIODIC or LB_COUETTE_Y */
   int32_t precision;  /* LB_FP64: populations stored and updated in FP64.
                          LB_FP32_DEV: stored and updated in FP32 as deviations
-                         f_is - w_i rho_ref_s; reductions stay FP64. */
+                         f_is - w_i rho_ref_s; reductions stay FP64.
+                         LB_FP32_MOM: for tau_A = tau_B = 1 only, where the
+                         collision sets every population to its equilibrium
+                         (Eq. (1)): the state is the post-collision rho_s - rho_ref_s
+                         and v_s of each site in FP32 (6 numbers instead of 18;
+                         the populations at t are the equilibria of the
+                         sources r - c_i).  Periodic boundaries only;
+                         lb_set_populations is not available.  Same model,
+                         different rounding from LB_FP32_DEV. */
   double tau[2];
   double rho0;
   double G_a[2];
@@ -302,7 +310,8 @@ int lb_pool_set_options(lb_pool* pool, int32_t keep_fields, int32_t use_graph);
 size_t lb_pool_job_bytes(const lb_params* p);
 /* Queue a job of `steps` steps (p->device_buffer ignored), started from the
  * lb_init_noise state or from host densities (copied at submission).
- * LB_E_NOMEM if its footprint alone exceeds the budget. */
+ * LB_E_NOMEM if its footprint alone exceeds the budget; LB_E_INVAL for
+ * LB_FP32_MOM (the pool runs population storage). */
 int lb_pool_submit_noise(lb_pool* pool, const lb_params* p, uint64_t seed, double mean_a,
                          double mean_b, double amp, int64_t steps, int64_t* job_id);
 int lb_pool_submit(lb_pool* pool, const lb_params* p, const double* rho_a, const double* rho_b,

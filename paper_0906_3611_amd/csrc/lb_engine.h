@@ -36,6 +36,7 @@ struct Member {
 struct Engine {
   std::vector<Member> m;
   bool fp64 = true, walls = false;
+  bool mom = false;           // LB_FP32_MOM storage (moment kernels)
   hipStream_t stream = nullptr;
   hipStream_t capture_stream = nullptr;
   int device = 0;

@@ -3,6 +3,7 @@
 #include "lb_engine.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -39,7 +40,7 @@ lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   g.nx = p->nx;
   g.ny = p->ny;
   g.pitch = (p->nx + lbk::kWave - 1) / lbk::kWave * lbk::kWave;  // strips start on a line
-  g.row_elems = (long long)(g.pitch / lbk::kWave) * 18 * lbk::kWave;
+  g.row_elems = (long long)(g.pitch / lbk::kWave) * (p->precision == LB_FP32_MOM ? 6 : 18) * lbk::kWave;
   g.nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
   const int h0 = base_seg_h(p);
   int nsegs = std::max((p->ny + h0 - 1) / h0, (target_tiles(p) + g.nstrips - 1) / g.nstrips);
@@ -357,10 +358,15 @@ void set_rho_ref(Engine& E, int i, const double* ra, const double* rb, size_t n)
 int init_from_device_rho(Engine& E, int i, const double* d_rho, const double* d_u) {
   Member& mm = E.m[i];
   begin_member(E, i, 0);
+  mm.d.local[0] = E.mom ? 1 : 0;  // buf[0] becomes the current buffer
+  mm.d.local[1] = 0;
   int rc = upload_descs(E);
   if (rc != LB_OK) return rc;
-  HIPCK(E, lbk::launch_init(mm.d.g, mm.d.c, E.fp64, E.walls, d_rho, d_u, mm.d.buf[0], mm.d.wall[0],
-                            E.stream));
+  if (E.mom)
+    HIPCK(E, lbk::launch_moment_init(mm.d.g, mm.d.c, d_rho, d_u, mm.d.buf[0], E.stream));
+  else
+    HIPCK(E, lbk::launch_init(mm.d.g, mm.d.c, E.fp64, E.walls, d_rho, d_u, mm.d.buf[0],
+                              mm.d.wall[0], E.stream));
   rc = zero_member_slots(E, i);
   if (rc != LB_OK) return rc;
   HIPCK(E, hipStreamSynchronize(E.stream));
@@ -371,12 +377,20 @@ int init_from_device_rho(Engine& E, int i, const double* d_rho, const double* d_
 // Capture runs on a private non-blocking stream (the caller's stream may be
 // the null stream, which cannot be captured); replays go to the caller's
 // stream.  The graph holds the two kernel nodes only.
+hipError_t step_launch(const Engine& E, const lbk::LaunchArgs& a, hipStream_t st) {
+  return E.mom ? lbk::launch_moment_step(a, E.variant, st)
+               : lbk::launch_step(a, E.fp64, E.walls, E.variant, st);
+}
+
+hipError_t observe_launch(const Engine& E, const lbk::LaunchArgs& a, hipStream_t st) {
+  return E.mom ? lbk::launch_moment_observe(a, st) : lbk::launch_observe(a, E.fp64, E.walls, st);
+}
+
 int capture_pair(Engine& E, int parity) {
   if (!E.capture_stream) HIPCK(E, hipStreamCreateWithFlags(&E.capture_stream, hipStreamNonBlocking));
   HIPCK(E, hipStreamBeginCapture(E.capture_stream, hipStreamCaptureModeThreadLocal));
   for (int k = 0; k < 2; ++k) {
-    const hipError_t le = lbk::launch_step(launch_args(E, (parity + k) & 1), E.fp64, E.walls,
-                                           E.variant, E.capture_stream);
+    const hipError_t le = step_launch(E, launch_args(E, (parity + k) & 1), E.capture_stream);
     if (le != hipSuccess) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(E.capture_stream, &g);
@@ -436,7 +450,12 @@ int validate(const lb_params* p, std::string* why) {
   if (p->nx < 5 || p->ny < 5) return bad("nx and ny must be >= 5");
   if ((long long)p->nx * p->ny > (1LL << 30)) return bad("lattice larger than 2^30 sites");
   if (p->boundary != LB_PERIODIC && p->boundary != LB_COUETTE_Y) return bad("unknown boundary");
-  if (p->precision != LB_FP64 && p->precision != LB_FP32_DEV) return bad("unknown precision");
+  if (p->precision != LB_FP64 && p->precision != LB_FP32_DEV && p->precision != LB_FP32_MOM)
+    return bad("unknown precision");
+  if (p->precision == LB_FP32_MOM) {
+    if (p->tau[0] != 1.0 || p->tau[1] != 1.0) return bad("moment storage needs tau_A = tau_B = 1");
+    if (p->boundary != LB_PERIODIC) return bad("moment storage supports periodic boundaries only");
+  }
   for (int s = 0; s < 2; ++s) {
     if (!is_finite(p->tau[s]) || !(p->tau[s] > 0.5)) return bad("tau must be > 1/2");
     if (!is_finite(p->G_a[s]) || !is_finite(p->G_r[s])) return bad("couplings must be finite");
@@ -470,6 +489,7 @@ size_t engine_static_bytes(const lb_params* ps, int n) {
 int engine_create_static(Engine& E, const lb_params* ps, int n, void* buffer, size_t buffer_bytes,
                          hipStream_t stream) {
   E.fp64 = ps[0].precision == LB_FP64;
+  E.mom = ps[0].precision == LB_FP32_MOM;
   E.walls = ps[0].boundary == LB_COUETTE_Y;
   E.stream = stream;
   if (hipGetDevice(&E.device) != hipSuccess) return E.fail(LB_E_DEVICE, "no HIP device");
@@ -636,9 +656,13 @@ int engine_step(Engine& E, int64_t n) {
     }
   }
   for (; k < n; ++k) {
-    HIPCK(E, lbk::launch_step(launch_args(E, (int)(E.step & 1)), E.fp64, E.walls, E.variant, E.stream));
+    HIPCK(E, step_launch(E, launch_args(E, (int)(E.step & 1)), E.stream));
     ++E.step;
   }
+  // every buffer written by a moment step is in pull form; the kernels
+  // cleared their destinations' flags, keep the host copy in step
+  if (E.mom && n > 0)
+    for (auto& mm : E.m) mm.d.local[0] = mm.d.local[1] = 0;
   return LB_OK;
 }
 
@@ -648,7 +672,7 @@ int engine_observables(Engine& E, lb_obs* out /*[n]*/) {
   if (E.m.empty()) return LB_OK;
   DeviceGuard dg(E.device);
   const int n = (int)E.m.size();
-  HIPCK(E, lbk::launch_observe(launch_args(E, (int)(E.step & 1)), E.fp64, E.walls, E.stream));
+  HIPCK(E, observe_launch(E, launch_args(E, (int)(E.step & 1)), E.stream));
   HIPCK(E, lbk::launch_reduce_lattices(E.d_descs, n, 0, E.red_out, 16, E.stream));
   HIPCK(E, lbk::launch_reduce_lattices(E.d_descs, n, 1, E.red_out + lbk::kNRed, 16, E.stream));
   std::vector<double> h((size_t)n * 16);
@@ -665,7 +689,7 @@ int engine_member_observables(Engine& E, int i, lb_obs* out) {
   if (i < 0 || i >= (int)E.m.size()) return E.fail(LB_E_INVAL, "lattice index out of range");
   if (!E.m[i].initialized) return E.fail(LB_E_STATE, "observables before lb_init");
   DeviceGuard dg(E.device);
-  HIPCK(E, lbk::launch_observe(member_args(E, i), E.fp64, E.walls, E.stream));
+  HIPCK(E, observe_launch(E, member_args(E, i), E.stream));
   double* row = E.red_out + (size_t)i * 16;
   HIPCK(E, lbk::launch_reduce_lattices(E.d_descs + i, 1, 0, row, 16, E.stream));
   HIPCK(E, lbk::launch_reduce_lattices(E.d_descs + i, 1, 1, row + lbk::kNRed, 16, E.stream));
@@ -689,7 +713,7 @@ int engine_fields(Engine& E, int i, double* rho_a, double* rho_b, double* u, dou
   double* d = (double*)t.p;
   lbk::LaunchArgs a = member_args(E, i);
   a.fields = d;
-  HIPCK(E, lbk::launch_observe(a, E.fp64, E.walls, E.stream));
+  HIPCK(E, observe_launch(E, a, E.stream));
   if (rho_a) HIPCK(E, hipMemcpyAsync(rho_a, d, nb, hipMemcpyDeviceToHost, E.stream));
   if (rho_b) HIPCK(E, hipMemcpyAsync(rho_b, d + n, nb, hipMemcpyDeviceToHost, E.stream));
   if (u) HIPCK(E, hipMemcpyAsync(u, d + 2 * n, 2 * nb, hipMemcpyDeviceToHost, E.stream));
@@ -706,13 +730,14 @@ int engine_pops(Engine& E, int i, double* f) {
   HIPCK(E, hipMalloc(&t.p, nb));
   lbk::LaunchArgs a = member_args(E, i);
   a.pops = (double*)t.p;
-  HIPCK(E, lbk::launch_observe(a, E.fp64, E.walls, E.stream));
+  HIPCK(E, observe_launch(E, a, E.stream));
   HIPCK(E, hipMemcpyAsync(f, t.p, nb, hipMemcpyDeviceToHost, E.stream));
   return read_flags(E, nullptr);
 }
 
 int engine_set_pops(Engine& E, int i, const double* f, int64_t member_t) {
   if (i < 0 || i >= (int)E.m.size() || !f) return E.fail(LB_E_INVAL, "bad lattice index or NULL f");
+  if (E.mom) return E.fail(LB_E_INVAL, "moment storage cannot hold arbitrary populations");
   if (member_t < 0) return E.fail(LB_E_INVAL, "step must be >= 0");
   Member& mm = E.m[i];
   const size_t n = (size_t)mm.d.g.nx * mm.d.g.ny;
@@ -872,6 +897,8 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   }
   const int64_t step0 = E.step;
   const int seg0 = E.seg_h;
+  std::vector<std::array<int, 2>> local0;  // buffer forms of the moment storage
+  for (auto& mm : E.m) local0.push_back({mm.d.local[0], mm.d.local[1]});
   Events ev;
   HIPCK(E, hipEventCreate(&ev.e[0]));
   HIPCK(E, hipEventCreate(&ev.e[1]));
@@ -917,7 +944,8 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   }
   if (rc == LB_OK) {
     const lbk::StepVariant v1 = best_v;
-    for (int pf = 0; pf < 3 && rc == LB_OK; ++pf)
+    const int npf = E.mom ? 1 : 3;  // the moment kernel has no prefetch variants
+    for (int pf = 0; pf < npf && rc == LB_OK; ++pf)
       for (int nt = 0; nt < 2; ++nt) {
         const lbk::StepVariant v{pf, nt};
         if (v.prefetch == v1.prefetch && v.stream_stores == v1.stream_stores) continue;
@@ -932,7 +960,11 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   E.variant = best_v;
   E.variant_forced = true;
   E.seg_h = best_h;
-  const int rc2 = retile(E);
+  for (size_t i = 0; i < E.m.size(); ++i) {
+    E.m[i].d.local[0] = local0[i][0];
+    E.m[i].d.local[1] = local0[i][1];
+  }
+  const int rc2 = retile(E);  // uploads the descriptors with the restored forms
   off = 0;
   for (auto& mm : E.m) {
     HIPCK(E, hipMemcpyAsync(mm.region, (char*)save.p + off, mm.region_bytes, hipMemcpyDeviceToDevice,

@@ -53,6 +53,7 @@ struct Coefs {
 struct Geometry {
   int nx, ny, pitch;
   long long row_elems;  // elements of one lattice row: (pitch / 64) blocks x 18 x 64
+                        // (x 6 x 64 for moment storage)
   int nstrips, seg_h, nsegs, ntiles;  // tiles = strips x segments, one wavefront each
 };
 
@@ -68,6 +69,7 @@ struct LatticeDesc {
   double* wave_wall;  // step: wall-momentum accumulators (bottom, top) per strip
   int tile_base;  // first tile of this lattice in its launch's tile list
   int phase;      // with launch step parity p the lattice reads buf[p ^ phase]
+  int local[2];   // moment storage: buf[k] holds site-local equilibria (t = 0 form)
 };
 
 // Arguments of one step / observe launch over a set of lattices that share
@@ -106,6 +108,12 @@ hipError_t launch_init(const Geometry& g, const Coefs& c, bool fp64, bool walls,
 // Same from host-supplied populations f[2][9][ny][nx] (device copy).
 hipError_t launch_set_pops(const Geometry& g, const Coefs& c, bool fp64, bool walls,
                            const double* f, void* buf, void* wall, hipStream_t st);
+// Moment storage at tau = 1 (lb_moment.hip): step and observe launches over
+// the same LaunchArgs, and the t = 0 state in local form from FP64 fields.
+hipError_t launch_moment_step(const LaunchArgs& a, const StepVariant& v, hipStream_t st);
+hipError_t launch_moment_observe(const LaunchArgs& a, hipStream_t st);
+hipError_t launch_moment_init(const Geometry& g, const Coefs& c, const double* rho /*[2][ny][nx]*/,
+                              const double* u /*[2][ny][nx] or null*/, void* buf, hipStream_t st);
 // Counter-based noise densities rho_s = mean_s + amp (2U - 1) into rho[2][ny][nx].
 hipError_t launch_noise(int nx, int ny, uint64_t seed, double mean_a, double mean_b, double amp,
                         double* rho, hipStream_t st);

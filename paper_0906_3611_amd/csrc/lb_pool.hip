@@ -196,6 +196,7 @@ size_t lb_pool_job_bytes(const lb_params* p) {
 static int submit_common(lb_pool* P, const lb_params* p, int64_t steps, Job& j, int64_t* job_id) {
   std::string why;
   if (lbe::validate(p, &why) != LB_OK) return P->fail(LB_E_INVAL, why);
+  if (p->precision == LB_FP32_MOM) return P->fail(LB_E_INVAL, "the pool runs population storage only");
   if (steps < 0) return P->fail(LB_E_INVAL, "steps must be >= 0");
   j.p = *p;
   j.p.device_buffer = nullptr;

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "lb.h")
 
 LB_OK, LB_E_INVAL, LB_E_NOMEM, LB_E_DEVICE, LB_E_UNSTABLE, LB_E_STATE = 0, -1, -2, -3, -4, -5
 LB_PERIODIC, LB_COUETTE_Y = 0, 1
-LB_FP64, LB_FP32_DEV = 0, 1
+LB_FP64, LB_FP32_DEV, LB_FP32_MOM = 0, 1, 2
 
 
 class LBError(RuntimeError):
@@ -172,7 +172,7 @@ def make_params(nx, ny, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1
     p = lb_params()
     p.nx, p.ny = int(nx), int(ny)
     p.boundary = {"periodic": LB_PERIODIC, "couette": LB_COUETTE_Y}[boundary]
-    p.precision = {"fp64": LB_FP64, "fp32dev": LB_FP32_DEV}[precision]
+    p.precision = {"fp64": LB_FP64, "fp32dev": LB_FP32_DEV, "fp32mom": LB_FP32_MOM}[precision]
     p.tau[0], p.tau[1] = tau
     p.rho0 = rho0
     p.G_a[0], p.G_a[1] = G_a
