@@ -28,9 +28,12 @@ if ROOT not in sys.path:
 
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 PAPER_MLUPS = 1024 * 1024 * 1e6 / 86400 / 1e6  # 1024^2, 1e6 steps in about one day (Appendix)
-BYTES_PER_SITE = {"fp32dev": 144, "fp64": 288}  # 2 species x 9 populations x (read + write)
+# 2 species x 9 populations x (read + write); the tau = 1 moment storage
+# reads and writes 2 species x (rho, v_x, v_y) in FP32 per site
+BYTES_PER_SITE = {"fp32dev": 144, "fp64": 288, "fp32mom": 48}
 PARAMS = dict(tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405)
-KERNEL_SRC = os.path.join(ROOT, "paper_0906_3611_amd", "csrc", "lb_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_0906_3611_amd", "csrc", f)
+               for f in ("lb_kernels.hip", "lb_moment.hip", "lb_device.h", "lb_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 
 
@@ -44,8 +47,12 @@ def code_hash(text: str) -> str:
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SRC) as fh:
-        return code_hash(fh.read())
+    """Code hash over every source the step kernels are compiled from."""
+    text = ""
+    for path in KERNEL_SRCS:
+        with open(path) as fh:
+            text += fh.read()
+    return code_hash(text)
 
 
 def ensure_built():
@@ -125,6 +132,34 @@ def cpu_baseline(nx, ny, rho_a, rho_b, budget_s=10.0):
             "sample": f"{nx}x{ny} disc emulsion, FP64, {n} steps after 1 untimed, {dt:.1f} s",
             "value_1_thread": v1, "sample_1_thread": f"{n1} steps, {dt1:.1f} s",
             "cpu": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def bench_moment(nx, ny, steps, warmup, rho_a, rho_b, dev_run, r64, no_probe):
+    """The tau = 1 moment storage (48 B per site update) on the same
+    workload, with its density deviation from the population-storage runs,
+    and on a 4096^2 lattice whose 805 MB of state is HBM-resident."""
+    import numpy as np
+    r = run_gpu(nx, ny, "fp32mom", steps, warmup, rho_a, rho_b)
+    out = {"value": r["mlups"], "unit": "MLUPS", "ms_per_step": r["ms_per_step"],
+           "bytes_per_site": BYTES_PER_SITE["fp32mom"], "achieved_gbs": r["achieved_gbs"],
+           "frac": r["achieved_gbs"] / PEAK_HBM_GBS, "launch": r["info"],
+           "traffic": traffic_for("fp32mom", nx * ny),
+           "max_abs_rho_vs_fp32dev": float(np.abs(r["rho"] - dev_run["rho"]).max()),
+           "mass": list(r["obs"]["mass"])}
+    if r64 is not None:
+        out["max_abs_rho_vs_fp64"] = float(np.abs(r["rho"] - r64["rho"]).max())
+    if not no_probe:
+        qa, qb = inputs_noise(4096, 4096)
+        pq = run_gpu(4096, 4096, "fp32mom", 1000, 50, qa, qb)
+        out["hbm_probe_4096x4096"] = {"value": pq["mlups"], "ms_per_step": pq["ms_per_step"],
+                                      "achieved_gbs": pq["achieved_gbs"],
+                                      "frac": pq["achieved_gbs"] / PEAK_HBM_GBS}
+    return out
+
+
+def inputs_noise(nx, ny):
+    from paper_0906_3611_amd import inputs
+    return inputs.noise_fields(nx, ny, 3, 0.5, 0.5, 0.01)
 
 
 def _timed(stream, fn):
@@ -520,11 +555,14 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
             raise SystemExit(f"no matching dispatches in {path}")
         return statistics.median(vals)
 
-    def step(n):  # step-mode launches of the march kernel (template argument MODE = 0)
-        if "k_march<" not in n:
+    # step-mode launches (template argument MODE = 0) of the precision's kernel
+    kname, nargs, mode_at = ("k_moment<", 3, 1) if precision == "fp32mom" else ("k_march<", 7, 4)
+
+    def step(n):
+        if kname not in n:
             return False
-        args = n.split("k_march<", 1)[1].split(">", 1)[0].split(", ")
-        return len(args) == 7 and args[4] == "0"
+        args = n.split(kname, 1)[1].split(">", 1)[0].split(", ")
+        return len(args) == nargs and args[mode_at] == "0"
     copy = lambda n: "copyBuffer" in n
     kib = copy_bytes / 1024
     f_scale = kib / per_dispatch(copy_fetch_csv, copy)
@@ -564,7 +602,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=1024)
-    ap.add_argument("--precision", choices=["fp32dev", "fp64"], default="fp32dev")
+    ap.add_argument("--precision", choices=["fp32dev", "fp64", "fp32mom"], default="fp32dev")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the 4096x1024 HBM-resident probe")
@@ -572,6 +610,7 @@ def main():
     ap.add_argument("--no-couette", action="store_true", help="skip the Couette channel runs")
     ap.add_argument("--no-kolmogorov", action="store_true", help="skip the shear-forcing protocol")
     ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 error study")
+    ap.add_argument("--no-moment", action="store_true", help="skip the tau = 1 moment-storage runs")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 100-realization ensemble")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
@@ -612,6 +651,7 @@ def main():
           f"{main_run['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
 
     extra = {}
+    r64 = None
     if not args.no_fp64 and args.precision != "fp64":
         r64 = run_gpu(nx, ny, "fp64", args.steps, args.warmup, rho_a, rho_b)
         extra["fp64"] = {"value": r64["mlups"], "ms_per_step": r64["ms_per_step"],
@@ -636,6 +676,11 @@ def main():
                                         "frac": pq["achieved_gbs"] / PEAK_HBM_GBS}
         print(f"# probe 4096x4096: {pq['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
+    if not args.no_moment and args.precision != "fp32mom":
+        extra["moment_tau1"] = bench_moment(nx, ny, args.steps, args.warmup, rho_a, rho_b,
+                                            main_run, r64, args.no_probe)
+        print(f"# fp32mom {nx}x{ny}: {extra['moment_tau1']['value']:.0f} MLUPS", file=sys.stderr,
+              flush=True)
     if not args.no_precision and (nx, ny) == (1024, 1024):
         extra["precision_c2"] = bench_precision(nx, ny, rho_a, rho_b)
         print("# precision study done", file=sys.stderr, flush=True)
