@@ -31,6 +31,7 @@ PAPER_MLUPS = 1024 * 1024 * 1e6 / 86400 / 1e6  # 1024^2, 1e6 steps in about one 
 # 2 species x 9 populations x (read + write); the tau = 1 moment storage
 # reads and writes 2 species x (rho, v_x, v_y) in FP32 per site
 BYTES_PER_SITE = {"fp32dev": 144, "fp64": 288, "fp32mom": 48}
+STEP_KERNEL = {"fp32dev": "k_march (step)", "fp64": "k_march (step)", "fp32mom": "k_mstep"}
 PARAMS = dict(tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_0906_3611_amd", "csrc", f)
                for f in ("lb_kernels.hip", "lb_moment.hip", "lb_device.h", "lb_internal.h")]
@@ -556,13 +557,13 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
         return statistics.median(vals)
 
     # step-mode launches (template argument MODE = 0) of the precision's kernel
-    kname, nargs, mode_at = ("k_moment<", 3, 1) if precision == "fp32mom" else ("k_march<", 7, 4)
+    kname, nargs, mode_at = ("k_mstep<", 1, None) if precision == "fp32mom" else ("k_march<", 7, 4)
 
     def step(n):
         if kname not in n:
             return False
         args = n.split(kname, 1)[1].split(">", 1)[0].split(", ")
-        return len(args) == nargs and args[mode_at] == "0"
+        return len(args) == nargs and (mode_at is None or args[mode_at] == "0")
     copy = lambda n: "copyBuffer" in n
     kib = copy_bytes / 1024
     f_scale = kib / per_dispatch(copy_fetch_csv, copy)
@@ -705,7 +706,7 @@ def main():
     roof = {"bound": "hbm", "achieved": main_run["achieved_gbs"], "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": main_run["achieved_gbs"] / PEAK_HBM_GBS,
             "traffic": traffic_for(args.precision, sites),
-            "kernel": "k_march (step)", "bytes_per_site": BYTES_PER_SITE[args.precision],
+            "kernel": STEP_KERNEL[args.precision], "bytes_per_site": BYTES_PER_SITE[args.precision],
             "units_per_launch": sites,
             # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed
             "cache_resident": pop_bytes <= (256 << 20)}
@@ -720,7 +721,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": main_run["mlups"] / PAPER_MLUPS,
-        "dtype": "f32" if args.precision == "fp32dev" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{nx}x{ny} periodic two-species Shan-Chen D2Q9, seeded disc "
                                f"emulsion phi=0.7, rho0=0.83 standard couplings, "
