@@ -31,10 +31,12 @@ PAPER_MLUPS = 1024 * 1024 * 1e6 / 86400 / 1e6  # 1024^2, 1e6 steps in about one 
 # 2 species x 9 populations x (read + write); the tau = 1 moment storage
 # reads and writes 2 species x (rho, v_x, v_y) in FP32 per site
 BYTES_PER_SITE = {"fp32dev": 144, "fp64": 288, "fp32mom": 48}
-STEP_KERNEL = {"fp32dev": "k_march (step)", "fp64": "k_march (step)", "fp32mom": "k_mstep"}
+# step kernel of each storage on a periodic lattice
+STEP_KERNEL = {"fp32dev": "k_split", "fp64": "k_march (step)", "fp32mom": "k_mstep"}
 PARAMS = dict(tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405)
 KERNEL_SRCS = [os.path.join(ROOT, "paper_0906_3611_amd", "csrc", f)
-               for f in ("lb_kernels.hip", "lb_moment.hip", "lb_device.h", "lb_internal.h")]
+               for f in ("lb_kernels.hip", "lb_split.hip", "lb_moment.hip", "lb_device.h",
+                         "lb_internal.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 
 
@@ -557,7 +559,8 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
         return statistics.median(vals)
 
     # step-mode launches (template argument MODE = 0) of the precision's kernel
-    kname, nargs, mode_at = ("k_mstep<", 1, None) if precision == "fp32mom" else ("k_march<", 7, 4)
+    kname, nargs, mode_at = {"fp32mom": ("k_mstep<", 1, None), "fp32dev": ("k_split<", 5, None),
+                             "fp64": ("k_march<", 7, 4)}[precision]
 
     def step(n):
         if kname not in n:

@@ -273,14 +273,15 @@ int retile(Engine& E) {
 
 void choose_default_variant(Engine& E) {
   // Defaults (measured): streaming stores when the population buffers
-  // exceed the 256 MB Infinity Cache.  FP32: no prefetch then (three waves
+  // exceed the 256 MB Infinity Cache.  Periodic FP32 (one wave per species,
+  // four per SIMD): no prefetch.  FP32 walls: no prefetch then (three waves
   // per SIMD), a one-row prefetch when they fit.  FP64 (one wave per SIMD):
   // always a one-row prefetch.
   if (E.variant_forced) return;
   size_t total_pop = 0;
   for (auto& mm : E.m) total_pop += 2 * mm.pop_bytes;
   const bool hbm = total_pop > kInfinityCacheBytes;
-  E.variant.prefetch = (E.fp64 || !hbm) ? 1 : 0;
+  E.variant.prefetch = split_kernel(E) ? 0 : ((E.fp64 || !hbm) ? 1 : 0);
   E.variant.stream_stores = hbm ? 1 : 0;
   if (const char* e = std::getenv("LBSOFT_PREFETCH"))
     E.variant.prefetch = std::max(0, std::min(std::atoi(e), 2));
@@ -378,8 +379,9 @@ int init_from_device_rho(Engine& E, int i, const double* d_rho, const double* d_
 // the null stream, which cannot be captured); replays go to the caller's
 // stream.  The graph holds the two kernel nodes only.
 hipError_t step_launch(const Engine& E, const lbk::LaunchArgs& a, hipStream_t st) {
-  return E.mom ? lbk::launch_moment_step(a, E.variant, st)
-               : lbk::launch_step(a, E.fp64, E.walls, E.variant, st);
+  if (E.mom) return lbk::launch_moment_step(a, E.variant, st);
+  if (split_kernel(E)) return lbk::launch_split_step(a, E.fp64, E.variant, st);
+  return lbk::launch_step(a, E.fp64, E.walls, E.variant, st);
 }
 
 hipError_t observe_launch(const Engine& E, const lbk::LaunchArgs& a, hipStream_t st) {

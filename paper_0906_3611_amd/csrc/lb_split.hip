@@ -1,0 +1,230 @@
+// Step kernel of periodic lattices with one wavefront per species
+// (population storage, FP32 deviations or FP64).
+//
+// The tiles, memory layout and march are those of k_march (lb_kernels.hip):
+// a workgroup owns a 64-column strip and a segment of rows and marches
+// along it, keeping rho and psi of five rows in an LDS ring.  Here the
+// workgroup has two wavefronts, wave s handling species s for all 64
+// columns: it pulls the 9 populations of its species (Eq. (1) LHS), forms
+// rho_s and psi_s (Eq. (5)), and, for the row two behind, the force on its
+// species (Eq. (2); the cross term reads the other species' density from
+// the ring) and the BGK update of its 9 populations.  The common velocity
+// u' couples the species: each wave puts the j_s of every row it pulls in
+// LDS and both evaluate u' by the same expression in the same order.  Per wave this halves the
+// registers and the instruction stream of a row, so twice as many waves
+// share the work and hide each other's latency; the HBM traffic is the
+// same.
+#include "lb_device.h"
+
+namespace lbk {
+namespace {
+
+template <typename ST, typename CT, bool DEV, int PF, bool NT>
+__global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
+  // Multiply-adds are fused only within one source expression, so every
+  // unrolled copy of the march rounds a site alike.
+#pragma clang fp contract(on)
+  constexpr int W = kWave + 4;     // ring entries per row
+  constexpr int NSET = 3 + PF;     // pulled rows held in registers
+  constexpr int kItems = 4 * 9;    // ring items of one species: 4 columns x 9 directions
+  // One barrier per row (after both waves have written it), so a wave can
+  // run one row ahead of the other: the ring keeps 6 rows (5 are read) and
+  // the momenta 4 (row k - 2 is read while row k + 1 may be written).
+  constexpr int kSRing = 6, kJRing = 4;
+  __shared__ CT ring_p[kSRing * W * 2];  // psi of the stencil rows, [slot][pos][species]
+  __shared__ CT ring_r[kSRing * W * 2];  // rho of the stencil rows
+  __shared__ CT rstage[2][kItems];       // pulled ring items of the current row, per species
+  __shared__ CT xj[kJRing][2][2][kWave];  // j_x, j_y of a pulled row, per species
+  const int b = blockIdx.x;
+  const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
+  if (tile >= a.ntiles) return;  // the whole workgroup leaves together
+  const int li = a.tile_lattice ? a.tile_lattice[tile] : 0;
+  const LatticeDesc* __restrict__ D = a.descs + li;
+  const Geometry g = D->g;
+  const int local = a.tile_lattice ? tile - D->tile_base : tile;
+  const int sel = (a.parity ^ D->phase) & 1;
+  const int strip = local % g.nstrips;
+  const int seg = local / g.nstrips;
+  const int s = threadIdx.x >> 6;  // species of this wave (uniform)
+  const int lane = threadIdx.x & (kWave - 1);
+  const int nx = g.nx, ny = g.ny;
+  const int x0 = strip * kWave;
+  const int width = min(kWave, nx - x0);
+  const int y0 = (int)((long long)seg * ny / g.nsegs);
+  const int y1 = (int)((long long)(seg + 1) * ny / g.nsegs);
+  const int dir = (seg & 1) ? -1 : 1;
+  const bool active = lane < width;
+  const int col = active ? x0 + lane : wrap(x0 + lane, nx);
+  constexpr uint32_t esz = sizeof(ST);
+  auto in_row = [&](int c) { return (uint32_t)((c >> 6) * (18 * kWave) + (c & 63)) * esz; };
+  const uint32_t ob_c = in_row(col);
+  const uint32_t ob_m = in_row(col == 0 ? nx - 1 : col - 1);
+  const uint32_t ob_p = in_row(col == nx - 1 ? 0 : col + 1);
+  // ring item of this lane (lanes 0..35): column rc of x0 - 2, x0 - 1,
+  // x0 + w, x0 + w + 1, direction ri; its source column and in-row offset
+  const bool rl = lane < kItems;
+  const int rc = lane & 3, ri = rl ? lane >> 2 : 0;
+  const int rcol = wrap(rc < 2 ? x0 - 2 + rc : x0 + width + (rc - 2), nx);
+  const int rsrc = wrap(rcol - cx(ri), nx);
+  const int rdy = cy(ri);
+  const uint32_t rob =
+      (uint32_t)((rsrc >> 6) * (18 * kWave) + (s * 9 + ri) * kWave + (rsrc & 63)) * esz;
+  // lanes 0..3 sum the ring column rc = lane; its ring position
+  const int rpos = lane < 2 ? lane : width + lane;
+
+  const Params<CT, DEV> P(D->c);
+  const ST* __restrict__ src = (const ST*)D->buf[sel];
+  ST* __restrict__ dst = (ST*)D->buf[sel ^ 1];
+  // per-species constants (selects: a uniform index into P would move it to memory)
+  const CT rref = s ? P.rref[1] : P.rref[0];
+  const CT pref = s ? P.pref[1] : P.pref[0];
+  const CT tau = s ? P.tau[1] : P.tau[0];
+  const CT om = s ? P.om[1] : P.om[0];
+  CT ks[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) ks[c] = s ? P.k[1][c] : P.k[0][c];
+
+  CT fr[NSET][9];  // pulled rows of this species, set k % NSET for march row k
+  ST rv[NSET];     // this lane's ring item of those rows
+  bool bad = false;
+  const int K = (y1 - y0) + 4;
+  const int rstart = dir > 0 ? y0 - 2 : y1 + 1;
+  auto lattice_row = [&](int k) {
+    const int r = rstart + dir * k;
+    return r < 0 ? r + ny : (r >= ny ? r - ny : r);
+  };
+  auto pull_row = [&](int k, CT (&f)[9], ST& v) {
+    const int re = lattice_row(k);
+    const int rm = re > 0 ? re - 1 : ny - 1, rp = re < ny - 1 ? re + 1 : 0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int row = cy(i) > 0 ? rm : (cy(i) < 0 ? rp : re);
+      const uint32_t ob = cx(i) > 0 ? ob_m : (cx(i) < 0 ? ob_p : ob_c);
+      const ST* base = src + (long long)row * g.row_elems + (s * 9 + i) * kWave;
+      f[i] = (CT)ld_at(base, ob);
+    }
+    const int row = rdy > 0 ? rm : (rdy < 0 ? rp : re);
+    v = rl ? ld_at(src + (long long)row * g.row_elems, rob) : ST(0);
+  };
+
+  static_for<PF>([&](auto Q) {
+    constexpr int q = decltype(Q)::value;
+    if (q < K) pull_row(q, fr[q], rv[q]);
+  });
+  for (int k0 = 0; k0 < K; k0 += NSET) {
+    static_for<NSET>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      const int k = k0 + j;
+      if (k >= K) return;
+      if (!PF) pull_row(k, fr[j], rv[j]);
+      // rho_s and psi_s of the pulled row into ring slot k % 5; the ring
+      // items go through LDS to lanes 0..3, which sum them in the same order
+      CT rho = fr[j][0];
+#pragma unroll
+      for (int i = 1; i < 9; ++i) rho += fr[j][i];
+      const CT psi = psi_of<CT, DEV>(P, s, rho);
+      if (rl) rstage[s][lane] = (CT)rv[j];
+      {
+        const CT(&f)[9] = fr[j];
+        xj[k % kJRing][s][0][lane] = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+        xj[k % kJRing][s][1][lane] = (f[2] - f[4]) + (f[5] - f[8]) + (f[6] - f[7]);
+      }
+      lds_fence();
+      const int slot = k % kSRing;
+      if (active) {
+        ring_p[(slot * W + lane + 2) * 2 + s] = psi;
+        ring_r[(slot * W + lane + 2) * 2 + s] = rho;
+      }
+      if (lane < 4) {
+        CT acc = rstage[s][lane];
+#pragma unroll
+        for (int i = 1; i < 9; ++i) acc += rstage[s][4 * i + lane];
+        ring_p[(slot * W + rpos) * 2 + s] = psi_of<CT, DEV>(P, s, acc);
+        ring_r[(slot * W + rpos) * 2 + s] = acc;
+      }
+      __syncthreads();  // both species' row k is in the ring
+      if (PF && k + PF < K) pull_row(k + PF, fr[(j + PF) % NSET], rv[(j + PF) % NSET]);
+      if (k >= 4) {
+        constexpr int jc = (j + NSET - 2) % NSET;  // set of march row k - 2
+        const CT(&f)[9] = fr[jc];
+        int rows[5];
+#pragma unroll
+        for (int d = 0; d < 5; ++d) rows[d] = ((k - 2 + dir * (d - 2)) % kSRing) * W + lane + 2;
+        auto psi_at = [&](int dy, int dx, int sp) { return ring_p[(rows[dy + 2] + dx) * 2 + sp]; };
+        auto rho_at = [&](int dy, int dx, int sp) { return ring_r[(rows[dy + 2] + dx) * 2 + sp]; };
+        const int y = lattice_row(k - 2);
+        const int so = s ^ 1;
+        // forces (Eq. (2)) on species s over the twelve +-c pairs
+        CT Sx = 0, Sy = 0, Xx = 0, Xy = 0;
+        if (active) {
+#pragma unroll
+          for (int m = 0; m < 12; ++m) {
+            const int px = pair_cx(m), py = pair_cy(m), kk = pair_class(m);
+            const CT d = psi_at(py, px, s) - psi_at(-py, -px, s);
+            if (px) Sx += (ks[kk] * (CT)px) * d;
+            if (py) Sy += (ks[kk] * (CT)py) * d;
+            if (m < 4) {
+              const CT e = rho_at(py, px, so) - rho_at(-py, -px, so);  // the other species acts
+              if (px) Xx += (P.kx[kk] * (CT)px) * e;
+              if (py) Xy += (P.kx[kk] * (CT)py) * e;
+            }
+          }
+          const int jr = (k - 2) % kJRing;
+          const CT J0x = xj[jr][0][0][lane], J1x = xj[jr][1][0][lane];
+          const CT J0y = xj[jr][0][1][lane], J1y = xj[jr][1][1][lane];
+          const CT c0a = rho_at(0, 0, 0), c0b = rho_at(0, 0, 1);
+          const CT rho0 = DEV ? P.rref[0] + c0a : c0a, rho1 = DEV ? P.rref[1] + c0b : c0b;
+          const CT drho = s ? c0b : c0a;  // deviation (DEV) or density of species s
+          const CT rho_s = s ? rho1 : rho0;
+          const CT psi_s = DEV ? pref + psi_at(0, 0, s) : psi_at(0, 0, s);
+          CT Fx = -psi_s * Sx - rho_s * Xx, Fy = -psi_s * Sy - rho_s * Xy;
+          if (P.g != CT(0)) Fx += rho_s * (P.g * sinpi_ct<CT>((CT)y * P.iny2));
+          if (!(rho_s > CT(0)) || !(rho_s < CT(1e30))) bad = true;
+          // common velocity (Eq. (1) and the definition of u below it)
+          const CT inv_den = rcp_ct(rho0 * P.om[0] + rho1 * P.om[1]);
+          const CT ux = (J0x * P.om[0] + J1x * P.om[1]) * inv_den;
+          const CT uy = (J0y * P.om[0] + J1y * P.om[1]) * inv_den;
+          // BGK relaxation towards the equilibrium at v_s = u' + tau_s F_s / rho_s
+          const CT ir = rcp_ct(rho_s);
+          const CT vx = ux + tau * Fx * ir;
+          const CT vy = uy + tau * Fy * ir;
+          const CT usq = CT(1.5) * (vx * vx + vy * vy);
+          ST* row = dst + (long long)y * g.row_elems + (s * 9) * kWave;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) {
+            const CT cu = (CT)cx(i) * vx + (CT)cy(i) * vy;
+            const CT poly = cu * (CT(3) + CT(4.5) * cu) - usq;
+            const CT feq = DEV ? wq<CT>(i) * (drho + rho_s * poly) : wq<CT>(i) * rho_s * (CT(1) + poly);
+            st_at<NT>(row + i * kWave, ob_c, (ST)(f[i] + om * (feq - f[i])));
+          }
+        }
+      }
+    });
+  }
+  if (__any(bad) && lane == 0) atomicOr(D->flag, 1);
+}
+
+template <typename ST, typename CT, bool DEV, int PF, bool NT>
+hipError_t launch_split_t(const LaunchArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL((k_split<ST, CT, DEV, PF, NT>), dim3(8 * a.tiles_per_xcd), dim3(2 * kWave), 0,
+                     st, a);
+  return hipGetLastError();
+}
+
+template <int PF, bool NT>
+hipError_t launch_split_p(const LaunchArgs& a, bool fp64, hipStream_t st) {
+  return fp64 ? launch_split_t<double, double, false, PF, NT>(a, st)
+              : launch_split_t<float, float, true, PF, NT>(a, st);
+}
+
+}  // namespace
+
+hipError_t launch_split_step(const LaunchArgs& a, bool fp64, const StepVariant& v, hipStream_t st) {
+  if (v.prefetch >= 2)
+    return v.stream_stores ? launch_split_p<2, true>(a, fp64, st) : launch_split_p<2, false>(a, fp64, st);
+  if (v.prefetch == 1)
+    return v.stream_stores ? launch_split_p<1, true>(a, fp64, st) : launch_split_p<1, false>(a, fp64, st);
+  return v.stream_stores ? launch_split_p<0, true>(a, fp64, st) : launch_split_p<0, false>(a, fp64, st);
+}
+
+}  // namespace lbk
