@@ -81,9 +81,9 @@ def time_steps(lat, steps: int, warmup: int):
     return e0.elapsed_time(e1)  # ms
 
 
-def run_gpu(nx, ny, precision, steps, warmup, rho_a, rho_b):
+def run_gpu(nx, ny, precision, steps, warmup, rho_a, rho_b, boundary="periodic", u_wall=0.0):
     from paper_0906_3611_amd import lb
-    lat = lb.Lattice(nx, ny, precision=precision, **PARAMS)
+    lat = lb.Lattice(nx, ny, precision=precision, boundary=boundary, u_wall=u_wall, **PARAMS)
     lat.init(rho_a, rho_b)
     ms = time_steps(lat, steps, warmup)
     obs = lat.observables()  # raises on instability
@@ -607,6 +607,9 @@ def main():
     ap.add_argument("--nx", type=int, default=1024)
     ap.add_argument("--ny", type=int, default=1024)
     ap.add_argument("--precision", choices=["fp32dev", "fp64", "fp32mom"], default="fp32dev")
+    ap.add_argument("--boundary", choices=["periodic", "couette"], default="periodic",
+                    help="main run only (couette: walls on y moving at -/+ --u-wall)")
+    ap.add_argument("--u-wall", type=float, default=0.005)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-probe", action="store_true", help="skip the 4096x1024 HBM-resident probe")
@@ -650,7 +653,12 @@ def main():
 
     nx, ny = args.nx, args.ny
     rho_a, rho_b = inputs.disc_fields(nx, ny, seed=2, phi=0.7)
-    main_run = run_gpu(nx, ny, args.precision, args.steps, args.warmup, rho_a, rho_b)
+    walls = args.boundary == "couette"
+    if walls and args.precision == "fp32mom":
+        print("the moment storage is periodic only", file=sys.stderr)
+        sys.exit(2)
+    main_run = run_gpu(nx, ny, args.precision, args.steps, args.warmup, rho_a, rho_b,
+                       args.boundary, args.u_wall if walls else 0.0)
     print(f"# {args.precision} {nx}x{ny}: {main_run['mlups']:.0f} MLUPS, "
           f"{main_run['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
 
@@ -708,8 +716,9 @@ def main():
     pop_bytes = BYTES_PER_SITE[args.precision] * sites  # both population buffers (half each)
     roof = {"bound": "hbm", "achieved": main_run["achieved_gbs"], "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": main_run["achieved_gbs"] / PEAK_HBM_GBS,
-            "traffic": traffic_for(args.precision, sites),
-            "kernel": STEP_KERNEL[args.precision], "bytes_per_site": BYTES_PER_SITE[args.precision],
+            "traffic": None if walls else traffic_for(args.precision, sites),
+            "kernel": "k_march (step, walls)" if walls else STEP_KERNEL[args.precision],
+            "bytes_per_site": BYTES_PER_SITE[args.precision],
             "units_per_launch": sites,
             # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed
             "cache_resident": pop_bytes <= (256 << 20)}
@@ -726,9 +735,11 @@ def main():
         "vs_baseline": main_run["mlups"] / PAPER_MLUPS,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{nx}x{ny} periodic two-species Shan-Chen D2Q9, seeded disc "
+        "config": {"workload": f"{nx}x{ny} "
+                               + (f"Couette (walls at -/+{args.u_wall})" if walls else "periodic")
+                               + f" two-species Shan-Chen D2Q9, seeded disc "
                                f"emulsion phi=0.7, rho0=0.83 standard couplings, "
-                               f"{args.precision} population storage",
+                               f"{args.precision} storage",
                    "nx": nx, "ny": ny, "precision": args.precision,
                    "launch": main_run["info"]},
         "roofline": roof,
