@@ -34,9 +34,12 @@ BYTES_PER_SITE = {"fp32dev": 144, "fp64": 288, "fp32mom": 48}
 # step kernel of each storage on a periodic lattice
 STEP_KERNEL = {"fp32dev": "k_split", "fp64": "k_march (step)", "fp32mom": "k_mstep"}
 PARAMS = dict(tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405)
-KERNEL_SRCS = [os.path.join(ROOT, "paper_0906_3611_amd", "csrc", f)
-               for f in ("lb_kernels.hip", "lb_split.hip", "lb_moment.hip", "lb_device.h",
-                         "lb_internal.h")]
+# sources of each storage's periodic step kernel (a measurement is valid
+# while they are unchanged)
+KERNEL_SRCS = {p: [os.path.join(ROOT, "paper_0906_3611_amd", "csrc", f)
+                   for f in (k, "lb_device.h", "lb_internal.h")]
+               for p, k in (("fp32dev", "lb_split.hip"), ("fp64", "lb_kernels.hip"),
+                            ("fp32mom", "lb_moment.hip"))}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
 
 
@@ -49,10 +52,10 @@ def code_hash(text: str) -> str:
     return hashlib.sha256("".join(text.split()).encode()).hexdigest()[:16]
 
 
-def kernel_hash() -> str:
-    """Code hash over every source the step kernels are compiled from."""
+def kernel_hash(precision: str) -> str:
+    """Code hash over the sources the precision's step kernel is compiled from."""
     text = ""
-    for path in KERNEL_SRCS:
+    for path in KERNEL_SRCS[precision]:
         with open(path) as fh:
             text += fh.read()
     return code_hash(text)
@@ -538,7 +541,7 @@ def traffic_for(precision, sites):
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     ent = rec.get(f"{precision}@{sites}")
-    if not ent or rec.get("kernel_sha256_16") != kernel_hash():
+    if not ent or ent.get("kernel_sha256_16") != kernel_hash(precision):
         return None
     return ent["bytes_per_launch"]
 
@@ -548,7 +551,8 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
     """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs into HBM
     bytes per step launch.  Each counter is scaled by what it reads for a
     plain copy of copy_bytes (the --copy-probe run), and the result is stored
-    with the hash of the kernel source it was measured on."""
+    with the hash of the kernel sources it was measured on (one record per
+    precision and size; records of other kernels are kept)."""
     import csv
     import statistics
 
@@ -576,9 +580,9 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
     rec = {}
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
-    if rec.get("kernel_sha256_16") != kernel_hash():
-        rec = {"kernel_sha256_16": kernel_hash()}
-    rec[f"{precision}@{sites}"] = {"sites": sites, "bytes_per_launch": fetch + write, "fetch_bytes": fetch,
+    rec.pop("kernel_sha256_16", None)  # older single-hash format
+    rec[f"{precision}@{sites}"] = {"kernel_sha256_16": kernel_hash(precision),
+                      "sites": sites, "bytes_per_launch": fetch + write, "fetch_bytes": fetch,
                       "write_bytes": write, "fetch_scale": f_scale, "write_scale": w_scale,
                       "algorithmic_bytes": BYTES_PER_SITE[precision] * sites}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)

@@ -78,6 +78,25 @@ __device__ __forceinline__ Coef coef_of(float rref, float r, float vx, float vy)
   return c;
 }
 
+// The LDS window of one row: each site's coefficients for both species, as
+// two species-major planes of 16-byte entries, so that a wave's accesses of
+// one species and one half are consecutive (no bank conflicts).
+struct alignas(16) F4 {
+  float x, y, z, w;
+};
+struct Window {
+  F4 a[2][kWin];  // bd, qxy, ax5, ay5
+  F4 b[2][kWin];  // bx, by, b0, r
+  __device__ __forceinline__ void put(int s, int pos, const Coef& c) {
+    a[s][pos] = F4{c.bd, c.qxy, c.ax5, c.ay5};
+    b[s][pos] = F4{c.bx, c.by, c.b0, c.r};
+  }
+  __device__ __forceinline__ Coef get(int s, int pos) const {
+    const F4 u = a[s][pos], v = b[s][pos];
+    return Coef{u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
+  }
+};
+
 // Contributions (density deviation and x momentum) of one source row to the
 // column between sources L (x - 1), M (x) and R (x + 1) of that row, in its
 // three roles.
@@ -112,7 +131,7 @@ constexpr int kRingW = kWave + 4;  // ring entries per row
 template <bool NT>
 __device__ __forceinline__ void mstep_tile(const LaunchArgs& a, const LatticeDesc* __restrict__ D,
                                            int local_tile, int sel, bool up, bool local,
-                                           Coef (*win)[2], Pr<float>* ring_p, Pr<float>* ring_r) {
+                                           Window& win, Pr<float>* ring_p, Pr<float>* ring_r) {
 #pragma clang fp contract(on)
   constexpr int W = kRingW;
   const Geometry g = D->g;
@@ -191,15 +210,15 @@ __device__ __forceinline__ void mstep_tile(const LaunchArgs& a, const LatticeDes
                               {(P.rref[1] + ld[3]) * ld[4], (P.rref[1] + ld[3]) * ld[5]}};
       if (p + 1 < NP) issue(p + 1);
       if (active) {
-        win[own][0] = c0;
-        win[own][1] = c1;
+        win.put(0, own, c0);
+        win.put(1, own, c1);
       }
-      if (hl) win[hpos][hs] = ch;
+      if (hl) win.put(hs, hpos, ch);
       lds_fence();
       {
         Part t[2];
-        partials(win[own - 1][0], c0, win[own + 1][0], t[0]);
-        partials(win[own - 1][1], c1, win[own + 1][1], t[1]);
+        partials(win.get(0, own - 1), c0, win.get(0, own + 1), t[0]);
+        partials(win.get(1, own - 1), c1, win.get(1, own + 1), t[1]);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
           qc[j][s] = local ? (s ? c1.r : c0.r) : t[s].c;
@@ -212,8 +231,8 @@ __device__ __forceinline__ void mstep_tile(const LaunchArgs& a, const LatticeDes
         }
         if (rl) {
           Part tr;
-          partials(win[rwin - 1][rsp], win[rwin][rsp], win[rwin + 1][rsp], tr);
-          rc[j] = local ? win[rwin][rsp].r : tr.c;
+          partials(win.get(rsp, rwin - 1), win.get(rsp, rwin), win.get(rsp, rwin + 1), tr);
+          rc[j] = local ? win.b[rsp][rwin].w : tr.c;
           rf[j] = local ? 0.f : (up ? tr.u : tr.d);
           rb[j] = local ? 0.f : (up ? tr.d : tr.u);
         }
@@ -328,7 +347,7 @@ __device__ __forceinline__ void mstep_tile(const LaunchArgs& a, const LatticeDes
 
 template <bool NT>
 __global__ __launch_bounds__(kWave) void k_mstep(const LaunchArgs a) {
-  __shared__ Coef win[kWin][2];
+  __shared__ Window win;
   __shared__ Pr<float> ring_p[kRing * kRingW];
   __shared__ Pr<float> ring_r[kRing * kRingW];
   const int b = blockIdx.x;

@@ -31,8 +31,10 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   // run one row ahead of the other: the ring keeps 6 rows (5 are read) and
   // the momenta 4 (row k - 2 is read while row k + 1 may be written).
   constexpr int kSRing = 6, kJRing = 4;
-  __shared__ CT ring_p[kSRing * W * 2];  // psi of the stencil rows, [slot][pos][species]
-  __shared__ CT ring_r[kSRing * W * 2];  // rho of the stencil rows
+  // psi and rho of the stencil rows, [species][slot][pos]: species-major so
+  // that a wave reading one species hits consecutive banks
+  __shared__ CT ring_p[2][kSRing * W];
+  __shared__ CT ring_r[2][kSRing * W];
   __shared__ CT rstage[2][kItems];       // pulled ring items of the current row, per species
   __shared__ CT xj[kJRing][2][2][kWave];  // j_x, j_y of a pulled row, per species
   const int b = blockIdx.x;
@@ -132,15 +134,15 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
       lds_fence();
       const int slot = k % kSRing;
       if (active) {
-        ring_p[(slot * W + lane + 2) * 2 + s] = psi;
-        ring_r[(slot * W + lane + 2) * 2 + s] = rho;
+        ring_p[s][slot * W + lane + 2] = psi;
+        ring_r[s][slot * W + lane + 2] = rho;
       }
       if (lane < 4) {
         CT acc = rstage[s][lane];
 #pragma unroll
         for (int i = 1; i < 9; ++i) acc += rstage[s][4 * i + lane];
-        ring_p[(slot * W + rpos) * 2 + s] = psi_of<CT, DEV>(P, s, acc);
-        ring_r[(slot * W + rpos) * 2 + s] = acc;
+        ring_p[s][slot * W + rpos] = psi_of<CT, DEV>(P, s, acc);
+        ring_r[s][slot * W + rpos] = acc;
       }
       __syncthreads();  // both species' row k is in the ring
       if (PF && k + PF < K) pull_row(k + PF, fr[(j + PF) % NSET], rv[(j + PF) % NSET]);
@@ -150,8 +152,8 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
         int rows[5];
 #pragma unroll
         for (int d = 0; d < 5; ++d) rows[d] = ((k - 2 + dir * (d - 2)) % kSRing) * W + lane + 2;
-        auto psi_at = [&](int dy, int dx, int sp) { return ring_p[(rows[dy + 2] + dx) * 2 + sp]; };
-        auto rho_at = [&](int dy, int dx, int sp) { return ring_r[(rows[dy + 2] + dx) * 2 + sp]; };
+        auto psi_at = [&](int dy, int dx, int sp) { return ring_p[sp][rows[dy + 2] + dx]; };
+        auto rho_at = [&](int dy, int dx, int sp) { return ring_r[sp][rows[dy + 2] + dx]; };
         const int y = lattice_row(k - 2);
         const int so = s ^ 1;
         // forces (Eq. (2)) on species s over the twelve +-c pairs
