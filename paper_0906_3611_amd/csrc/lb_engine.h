@@ -75,11 +75,11 @@ int engine_create_static(Engine& E, const lb_params* ps, int n, void* buffer, si
                          hipStream_t stream);
 // Dynamic engine: starts empty; members get their own allocations.
 int engine_create_dynamic(Engine& E, bool fp64, bool walls, hipStream_t stream);
-// Periodic FP32-deviation lattices step with one wavefront per species
-// (k_split); walls, FP64 and the moment storage use their own kernels.  The
-// choice depends only on the engine's class, never on tuning, so a lattice
-// evolves bit for bit alike alone, batched or pooled.
-inline bool split_kernel(const Engine& E) { return !E.fp64 && !E.walls && !E.mom; }
+// FP32-deviation lattices (periodic or with walls) step with one wavefront
+// per species (k_split); FP64 and the moment storage use their own kernels.
+// The choice depends only on the engine's class, never on tuning, so a
+// lattice evolves bit for bit alike alone, batched or pooled.
+inline bool split_kernel(const Engine& E) { return !E.fp64 && !E.mom; }
 int engine_add(Engine& E, const lb_params* p, int64_t tag, int* index);
 int engine_remove(Engine& E, int index);
 void engine_destroy(Engine& E);

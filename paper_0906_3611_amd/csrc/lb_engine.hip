@@ -273,10 +273,8 @@ int retile(Engine& E) {
 
 void choose_default_variant(Engine& E) {
   // Defaults (measured): streaming stores when the population buffers
-  // exceed the 256 MB Infinity Cache.  Periodic FP32 (one wave per species,
-  // four per SIMD): no prefetch.  FP32 walls: no prefetch then (three waves
-  // per SIMD), a one-row prefetch when they fit.  FP64 (one wave per SIMD):
-  // always a one-row prefetch.
+  // exceed the 256 MB Infinity Cache.  FP32 (one wave per species, four per
+  // SIMD): no prefetch.  FP64 (one wave per SIMD): a one-row prefetch.
   if (E.variant_forced) return;
   size_t total_pop = 0;
   for (auto& mm : E.m) total_pop += 2 * mm.pop_bytes;
@@ -380,7 +378,7 @@ int init_from_device_rho(Engine& E, int i, const double* d_rho, const double* d_
 // stream.  The graph holds the two kernel nodes only.
 hipError_t step_launch(const Engine& E, const lbk::LaunchArgs& a, hipStream_t st) {
   if (E.mom) return lbk::launch_moment_step(a, E.variant, st);
-  if (split_kernel(E)) return lbk::launch_split_step(a, E.fp64, E.variant, st);
+  if (split_kernel(E)) return lbk::launch_split_step(a, E.fp64, E.walls, E.variant, st);
   return lbk::launch_step(a, E.fp64, E.walls, E.variant, st);
 }
 

@@ -95,9 +95,10 @@ struct StepVariant {
 hipError_t launch_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
                        hipStream_t st);
 hipError_t launch_observe(const LaunchArgs& a, bool fp64, bool walls, hipStream_t st);
-// Periodic FP32-deviation step with one wavefront per species
-// (lb_split.hip); fp64 = true returns hipErrorInvalidValue.
-hipError_t launch_split_step(const LaunchArgs& a, bool fp64, const StepVariant& v, hipStream_t st);
+// FP32-deviation step with one wavefront per species, periodic or with
+// walls (lb_split.hip); fp64 = true returns hipErrorInvalidValue.
+hipError_t launch_split_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
+                             hipStream_t st);
 // Fixed-order per-lattice sums of the per-tile slots of each lattice of
 // descs[0..n): its kNRed observe values (which = 0) or its 2 wall
 // accumulators (which = 1), into out[m * out_stride + 0 ..).

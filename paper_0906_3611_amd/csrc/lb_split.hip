@@ -1,5 +1,5 @@
-// Step kernel of periodic lattices with one wavefront per species
-// (population storage, FP32 deviations; FP64 measured no faster than
+// Step kernel with one wavefront per species (population storage, FP32
+// deviations, periodic or with moving walls; FP64 measured no faster than
 // k_march and is not built here).
 //
 // The tiles, memory layout and march are those of k_march (lb_kernels.hip):
@@ -20,7 +20,7 @@
 namespace lbk {
 namespace {
 
-template <typename ST, typename CT, bool DEV, int PF, bool NT>
+template <typename ST, typename CT, bool DEV, bool WALLS, int PF, bool NT>
 __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   // Multiply-adds are fused only within one source expression, so every
   // unrolled copy of the march rounds a site alike.
@@ -38,6 +38,7 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   __shared__ CT ring_r[2][kSRing * W];
   __shared__ CT rstage[2][kItems];       // pulled ring items of the current row, per species
   __shared__ CT xj[kJRing][2][2][kWave];  // j_x, j_y of a pulled row, per species
+  __shared__ double wmom[2][2][kWave];   // walls: x momentum to [species][wall] per lane
   const int b = blockIdx.x;
   const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
   if (tile >= a.ntiles) return;  // the whole workgroup leaves together
@@ -70,6 +71,8 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   const int rcol = wrap(rc < 2 ? x0 - 2 + rc : x0 + width + (rc - 2), nx);
   const int rsrc = wrap(rcol - cx(ri), nx);
   const int rdy = cy(ri);
+  // walls: the wall-buffer link of a ring item whose source is the wall
+  const int rj = (ri == 2 || ri == 4) ? 0 : ((ri == 5 || ri == 7) ? 1 : 2);
   const uint32_t rob =
       (uint32_t)((rsrc >> 6) * (18 * kWave) + (s * 9 + ri) * kWave + (rsrc & 63)) * esz;
   // lanes 0..3 sum the ring column rc = lane; its ring position
@@ -78,6 +81,12 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   const Params<CT, DEV> P(D->c);
   const ST* __restrict__ src = (const ST*)D->buf[sel];
   ST* __restrict__ dst = (ST*)D->buf[sel ^ 1];
+  const ST* __restrict__ wall_in = (const ST*)D->wall[sel];
+  ST* __restrict__ wall_out = (ST*)D->wall[sel ^ 1];
+  if (WALLS) {  // a tile reaches each wall row at most once; lanes off the lattice add 0
+    wmom[s][0][lane] = 0.0;
+    wmom[s][1][lane] = 0.0;
+  }
   // per-species constants (selects: a uniform index into P would move it to memory)
   const CT rref = s ? P.rref[1] : P.rref[0];
   const CT pref = s ? P.pref[1] : P.pref[0];
@@ -94,11 +103,19 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   const int rstart = dir > 0 ? y0 - 2 : y1 + 1;
   auto lattice_row = [&](int k) {
     const int r = rstart + dir * k;
+    if (WALLS) return r < 0 ? -1 - r : (r >= ny ? 2 * ny - 1 - r : r);  // mirrored ghost rows
     return r < 0 ? r + ny : (r >= ny ? r - ny : r);
   };
   auto pull_row = [&](int k, CT (&f)[9], ST& v) {
     const int re = lattice_row(k);
-    const int rm = re > 0 ? re - 1 : ny - 1, rp = re < ny - 1 ? re + 1 : 0;
+    int rm, rp;
+    if (WALLS) {
+      rm = re > 0 ? re - 1 : 0;  // row 0's c_y = +1 links come from the wall buffer
+      rp = re < ny - 1 ? re + 1 : ny - 1;
+    } else {
+      rm = re > 0 ? re - 1 : ny - 1;
+      rp = re < ny - 1 ? re + 1 : 0;
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int row = cy(i) > 0 ? rm : (cy(i) < 0 ? rp : re);
@@ -106,8 +123,24 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
       const ST* base = src + (long long)row * g.row_elems + (s * 9 + i) * kWave;
       f[i] = (CT)ld_at(base, ob);
     }
+    if (WALLS) {
+      if (re == 0) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          f[wall_in_dir(0, j)] = (CT)to_global(wall_in)[((0 * 2 + s) * 3 + j) * nx + col];
+      }
+      if (re == ny - 1) {
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          f[wall_in_dir(1, j)] = (CT)to_global(wall_in)[((1 * 2 + s) * 3 + j) * nx + col];
+      }
+    }
     const int row = rdy > 0 ? rm : (rdy < 0 ? rp : re);
     v = rl ? ld_at(src + (long long)row * g.row_elems, rob) : ST(0);
+    if (WALLS && rl && ((re == 0 && rdy > 0) || (re == ny - 1 && rdy < 0))) {
+      const int wl = re == 0 ? 0 : 1;
+      v = to_global(wall_in)[((wl * 2 + s) * 3 + rj) * nx + rcol];
+    }
   };
 
   static_for<PF>([&](auto Q) {
@@ -193,41 +226,78 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
           const CT vy = uy + tau * Fy * ir;
           const CT usq = CT(1.5) * (vx * vx + vy * vy);
           ST* row = dst + (long long)y * g.row_elems + (s * 9) * kWave;
+          CT post[9];
 #pragma unroll
           for (int i = 0; i < 9; ++i) {
             const CT cu = (CT)cx(i) * vx + (CT)cy(i) * vy;
             const CT poly = cu * (CT(3) + CT(4.5) * cu) - usq;
             const CT feq = DEV ? wq<CT>(i) * (drho + rho_s * poly) : wq<CT>(i) * rho_s * (CT(1) + poly);
-            st_at<NT>(row + i * kWave, ob_c, (ST)(f[i] + om * (feq - f[i])));
+            post[i] = f[i] + om * (feq - f[i]);
+            st_at<NT>(row + i * kWave, ob_c, (ST)post[i]);
+          }
+          if (WALLS && (y == 0 || y == ny - 1)) {
+            // the links leaving towards a wall return with the moving-wall
+            // term (halfway bounce-back); their x momentum goes to the wall
+            const int wl = y == ny - 1 ? 1 : 0;
+            const CT uwall = wl ? P.uw : -P.uw;
+            double mom = 0.0;
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+              const int o0 = wall_out_dir(0, jj), o1 = wall_out_dir(1, jj);
+              const CT po = wl ? post[o1] : post[o0];
+              const int cxo = wl ? cx(o1) : cx(o0);
+              const CT corr = CT(6) * wq<CT>(o0) * rho_s * ((CT)cxo * uwall);
+              to_global(wall_out)[((wl * 2 + s) * 3 + jj) * nx + col] = (ST)(po - corr);
+              const double full = (double)po + (DEV ? wq<double>(o0) * (double)rref : 0.0);
+              mom += (double)cxo * (2.0 * full - (double)corr);
+            }
+            wmom[s][wl][lane] = mom;
           }
         }
       }
     });
   }
   if (__any(bad) && lane == 0) atomicOr(D->flag, 1);
+  if (WALLS && a.accumulate_wall && (y0 == 0 || y1 == ny)) {  // uniform over the workgroup
+    // wall momentum of this strip: per lane species A + species B, then a
+    // fixed lane tree; slot (strip, wall), added to only by the tile holding
+    // that wall's row
+    __syncthreads();
+    if (s == 0) {
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        if (m == 0 ? y0 != 0 : y1 != ny) continue;
+        double v = wmom[0][m][lane] + wmom[1][m][lane];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+        if (lane == 0) D->wave_wall[(long long)strip * 2 + m] += v;
+      }
+    }
+  }
 }
 
-template <typename ST, typename CT, bool DEV, int PF, bool NT>
+template <bool WALLS, int PF, bool NT>
 hipError_t launch_split_t(const LaunchArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_split<ST, CT, DEV, PF, NT>), dim3(8 * a.tiles_per_xcd), dim3(2 * kWave), 0,
-                     st, a);
+  hipLaunchKernelGGL((k_split<float, float, true, WALLS, PF, NT>), dim3(8 * a.tiles_per_xcd),
+                     dim3(2 * kWave), 0, st, a);
   return hipGetLastError();
 }
 
-template <int PF, bool NT>
-hipError_t launch_split_p(const LaunchArgs& a, bool fp64, hipStream_t st) {
-  if (fp64) return hipErrorInvalidValue;  // FP32 deviation storage only
-  return launch_split_t<float, float, true, PF, NT>(a, st);
+template <bool WALLS>
+hipError_t launch_split_w(const LaunchArgs& a, const StepVariant& v, hipStream_t st) {
+  if (v.prefetch >= 2)
+    return v.stream_stores ? launch_split_t<WALLS, 2, true>(a, st) : launch_split_t<WALLS, 2, false>(a, st);
+  if (v.prefetch == 1)
+    return v.stream_stores ? launch_split_t<WALLS, 1, true>(a, st) : launch_split_t<WALLS, 1, false>(a, st);
+  return v.stream_stores ? launch_split_t<WALLS, 0, true>(a, st) : launch_split_t<WALLS, 0, false>(a, st);
 }
 
 }  // namespace
 
-hipError_t launch_split_step(const LaunchArgs& a, bool fp64, const StepVariant& v, hipStream_t st) {
-  if (v.prefetch >= 2)
-    return v.stream_stores ? launch_split_p<2, true>(a, fp64, st) : launch_split_p<2, false>(a, fp64, st);
-  if (v.prefetch == 1)
-    return v.stream_stores ? launch_split_p<1, true>(a, fp64, st) : launch_split_p<1, false>(a, fp64, st);
-  return v.stream_stores ? launch_split_p<0, true>(a, fp64, st) : launch_split_p<0, false>(a, fp64, st);
+hipError_t launch_split_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
+                             hipStream_t st) {
+  if (fp64) return hipErrorInvalidValue;  // FP32 deviation storage only
+  return walls ? launch_split_w<true>(a, v, st) : launch_split_w<false>(a, v, st);
 }
 
 }  // namespace lbk
