@@ -572,14 +572,17 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
         return statistics.median(vals)
 
     # step-mode launches (template argument MODE = 0) of the precision's kernel
-    kname, nargs, mode_at = {"fp32mom": ("k_mstep<", 1, None), "fp32dev": ("k_split<", 5, None),
-                             "fp64": ("k_march<", 7, 4)}[precision]
+    # (name, template arguments, index and value of the argument that selects
+    # periodic step launches)
+    kname, nargs, at, val = {"fp32mom": ("k_mstep<", 1, None, None),
+                             "fp32dev": ("k_split<", 6, 3, "false"),    # WALLS
+                             "fp64": ("k_march<", 7, 4, "0")}[precision]  # MODE
 
     def step(n):
         if kname not in n:
             return False
         args = n.split(kname, 1)[1].split(">", 1)[0].split(", ")
-        return len(args) == nargs and (mode_at is None or args[mode_at] == "0")
+        return len(args) == nargs and (at is None or args[at] == val)
     copy = lambda n: "copyBuffer" in n
     kib = copy_bytes / 1024
     f_scale = kib / per_dispatch(copy_fetch_csv, copy)
@@ -730,7 +733,7 @@ def main():
     roof = {"bound": "hbm", "achieved": main_run["achieved_gbs"], "peak": PEAK_HBM_GBS,
             "unit": "GB/s", "frac": main_run["achieved_gbs"] / PEAK_HBM_GBS,
             "traffic": None if walls else traffic_for(args.precision, sites),
-            "kernel": "k_march (step, walls)" if walls else STEP_KERNEL[args.precision],
+            "kernel": STEP_KERNEL[args.precision] + (" (walls)" if walls else ""),
             "bytes_per_site": BYTES_PER_SITE[args.precision],
             "units_per_launch": sites,
             # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed
