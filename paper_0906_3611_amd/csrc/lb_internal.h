@@ -92,6 +92,8 @@ struct StepVariant {
 };
 
 // Launchers (lb_kernels.hip).  All return hipError_t of the launch.
+// launch_step: FP64 steps (FP32 deviation storage steps through
+// launch_split_step; fp64 = false returns hipErrorInvalidValue).
 hipError_t launch_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
                        hipStream_t st);
 hipError_t launch_observe(const LaunchArgs& a, bool fp64, bool walls, hipStream_t st);

@@ -20,6 +20,9 @@
 // Pulled populations stay in registers until their collision, so every
 // population is read from HBM once per step apart from the ring re-reads,
 // which neighbouring strips and segments bring into L2 at the same time.
+// This kernel steps FP64 lattices and observes every population-storage
+// lattice; FP32 deviation storage steps with one wavefront per species
+// (lb_split.hip).
 #include "lb_device.h"
 
 namespace lbk {
@@ -517,10 +520,7 @@ hipError_t launch_march(const LaunchArgs& a, bool fp64, bool walls, hipStream_t 
     else
       hipLaunchKernelGGL((k_march<double, double, false, false, MODE, PF, NT>), grid, block, 0, st, a);
   } else if constexpr (MODE == kStep) {
-    if (walls)
-      hipLaunchKernelGGL((k_march<float, float, true, true, MODE, PF, NT>), grid, block, 0, st, a);
-    else
-      hipLaunchKernelGGL((k_march<float, float, true, false, MODE, PF, NT>), grid, block, 0, st, a);
+    return hipErrorInvalidValue;  // FP32 deviation storage steps in k_split (lb_split.hip)
   } else {
     // observation of FP32 deviation storage is evaluated in FP64
     if (walls)
