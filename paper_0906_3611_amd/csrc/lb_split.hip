@@ -49,7 +49,8 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   const int sel = (a.parity ^ D->phase) & 1;
   const int strip = local % g.nstrips;
   const int seg = local / g.nstrips;
-  const int s = threadIdx.x >> 6;  // species of this wave (uniform)
+  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // species of this wave
+  // (readfirstlane: provably uniform, so per-species values live in scalar registers)
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = g.nx, ny = g.ny;
   const int x0 = strip * kWave;
@@ -62,8 +63,6 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   constexpr uint32_t esz = sizeof(ST);
   auto in_row = [&](int c) { return (uint32_t)((c >> 6) * (18 * kWave) + (c & 63)) * esz; };
   const uint32_t ob_c = in_row(col);
-  const uint32_t ob_m = in_row(col == 0 ? nx - 1 : col - 1);
-  const uint32_t ob_p = in_row(col == nx - 1 ? 0 : col + 1);
   // ring item of this lane (lanes 0..35): column rc of x0 - 2, x0 - 1,
   // x0 + w, x0 + w + 1, direction ri; its source column and in-row offset
   const bool rl = lane < kItems;
@@ -77,6 +76,24 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
       (uint32_t)((rsrc >> 6) * (18 * kWave) + (s * 9 + ri) * kWave + (rsrc & 63)) * esz;
   // lanes 0..3 sum the ring column rc = lane; its ring position
   const int rpos = lane < 2 ? lane : width + lane;
+  // The own pulls load each direction's run aligned (lane = column, one
+  // 256-byte run of the 64-site block) and move the c_x = +-1 directions by
+  // one lane in registers: loads shifted by a column straddle two blocks and
+  // cost the cache hierarchy far more.  Lanes 0 and 63 take their missing
+  // neighbour (columns x0 - 1 and x0 + 64) from edge items loaded by lanes
+  // 36..41 with the ring items: directions 1, 5, 8 at x0 - 1 and 3, 6, 7 at
+  // x0 + 64.  (In a ragged strip the first lane past the strip already holds
+  // the right neighbour column, wrapped.)
+  const bool el = lane >= kItems && lane < kItems + 6;
+  const int ee = lane - kItems;
+  const int edir = ee < 3 ? (ee == 0 ? 1 : (ee == 1 ? 5 : 8)) : (ee == 3 ? 3 : (ee == 4 ? 6 : 7));
+  const int ecol = wrap(ee < 3 ? x0 - 1 : x0 + kWave, nx);
+  // this lane's side load (ring item or edge item): source row offset and in-row offset
+  const int sdy = el ? cy(edir) : rdy;
+  const uint32_t sob =
+      el ? (uint32_t)((ecol >> 6) * (18 * kWave) + (s * 9 + edir) * kWave + (ecol & 63)) * esz : rob;
+  const bool sl = rl || el;
+  const bool lane0 = lane == 0, lane63 = lane == kWave - 1;
 
   const Params<CT, DEV> P(D->c);
   const ST* __restrict__ src = (const ST*)D->buf[sel];
@@ -116,13 +133,29 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
       rm = re > 0 ? re - 1 : ny - 1;
       rp = re < ny - 1 ? re + 1 : 0;
     }
+    {
+      const int row = sdy > 0 ? rm : (sdy < 0 ? rp : re);
+      v = sl ? ld_at(src + (long long)row * g.row_elems, sob) : ST(0);
+    }
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int row = cy(i) > 0 ? rm : (cy(i) < 0 ? rp : re);
-      const uint32_t ob = cx(i) > 0 ? ob_m : (cx(i) < 0 ? ob_p : ob_c);
       const ST* base = src + (long long)row * g.row_elems + (s * 9 + i) * kWave;
-      f[i] = (CT)ld_at(base, ob);
+      f[i] = (CT)ld_at(base, ob_c);
     }
+    // c_x = +1 comes from the column to the left, c_x = -1 from the right
+    static_for<9>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      if constexpr (cx(i) != 0) {
+        constexpr int e = cx(i) > 0 ? (i == 1 ? 0 : (i == 5 ? 1 : 2)) : (i == 3 ? 3 : (i == 6 ? 4 : 5));
+        constexpr int ctrl = cx(i) > 0 ? 0x138 : 0x130;  // DPP wave_shr:1 / wave_shl:1
+        const float edge = __builtin_bit_cast(
+            float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, (float)v), kItems + e));
+        const int moved =
+            __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, (float)f[i]), ctrl, 0xF, 0xF, false);
+        f[i] = (CT)((cx(i) > 0 ? lane0 : lane63) ? edge : __builtin_bit_cast(float, moved));
+      }
+    });
     if (WALLS) {
       if (re == 0) {
 #pragma unroll
@@ -135,8 +168,6 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
           f[wall_in_dir(1, j)] = (CT)to_global(wall_in)[((1 * 2 + s) * 3 + j) * nx + col];
       }
     }
-    const int row = rdy > 0 ? rm : (rdy < 0 ? rp : re);
-    v = rl ? ld_at(src + (long long)row * g.row_elems, rob) : ST(0);
     if (WALLS && rl && ((re == 0 && rdy > 0) || (re == ny - 1 && rdy < 0))) {
       const int wl = re == 0 ? 0 : 1;
       v = to_global(wall_in)[((wl * 2 + s) * 3 + rj) * nx + rcol];
