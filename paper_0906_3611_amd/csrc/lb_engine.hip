@@ -45,9 +45,6 @@ lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   const int h0 = base_seg_h(p);
   int nsegs = std::max((p->ny + h0 - 1) / h0, (target_tiles(p) + g.nstrips - 1) / g.nstrips);
   nsegs = std::min(nsegs, std::max(1, p->ny / 8));
-  if (seg_h <= 0) {
-    if (const char* e = std::getenv("LBSOFT_SEG_H")) seg_h = std::atoi(e);
-  }
   if (seg_h >= 4) nsegs = (p->ny + seg_h - 1) / seg_h;
   nsegs = std::max(1, std::min(nsegs, p->ny));
   g.nsegs = nsegs;
@@ -281,10 +278,6 @@ void choose_default_variant(Engine& E) {
   const bool hbm = total_pop > kInfinityCacheBytes;
   E.variant.prefetch = split_kernel(E) ? 0 : ((E.fp64 || !hbm) ? 1 : 0);
   E.variant.stream_stores = hbm ? 1 : 0;
-  if (const char* e = std::getenv("LBSOFT_PREFETCH"))
-    E.variant.prefetch = std::max(0, std::min(std::atoi(e), 2));
-  if (const char* e = std::getenv("LBSOFT_STREAM_STORES"))
-    E.variant.stream_stores = std::atoi(e) ? 1 : 0;
 }
 
 lbk::LaunchArgs launch_args(const Engine& E, int parity) {
