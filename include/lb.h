@@ -190,9 +190,11 @@ int64_t lb_current_step(const lb_lattice* lat);
 
 /* How a step is launched: each lattice is cut into nstrips column strips of
  * 64 columns (the last may be narrower) and nsegs row segments of about
- * seg_h rows; each (strip, segment) tile is one 64-lane wavefront (one
- * workgroup), grid_blocks workgroups per step.  prefetch / stream_stores /
- * use_graph report the code variant in use (1 = on). */
+ * seg_h rows; each (strip, segment) tile is one workgroup of block_threads
+ * lanes (128 for FP32 deviation storage, one 64-lane wavefront per species;
+ * 64 for the FP64 and moment storages, one wavefront for both species),
+ * grid_blocks workgroups per step.  prefetch / stream_stores / use_graph
+ * report the code variant in use (1 = on). */
 typedef struct {
   int32_t nstrips, nsegs, ntiles, grid_blocks, block_threads, pitch;
   size_t workspace_bytes;
@@ -206,7 +208,7 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
  * strip partials, not over tiles).  Any argument < 0 keeps the current choice.
  *   seg_h: row-segment height (0 = default policy); wall averages carry on.
  *   prefetch: rows whose loads are in flight ahead of the current one
- *     (0, 1 or 2; larger values mean 2).
+ *     (0, 1 or 2; larger values mean 2; the moment storage ignores it).
  *   stream_stores: nontemporal population stores.
  *   use_graph: replay lb_step as captured two-step HIP graphs. */
 int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
@@ -215,7 +217,9 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
 /* Autotuner: time candidate launch shapes on the lattice's current state and
  * keep the fastest.  Candidates are the default policy and forced segment
  * heights of 8 to 256 rows with the current code variant, then the six
- * prefetch (0..2) / stream_stores variants at the best height; each runs 2 untimed
+ * prefetch (0..2) / stream_stores variants at the best height (the moment
+ * storage has no prefetch variants: only its two stream_stores variants are
+ * timed there); each runs 2 untimed
  * steps and then `steps` (>= 2, rounded up to even) timed with HIP events on
  * the lattice's stream.  Results are kept for the life of the process, by
  * GPU architecture, precision, boundary type, graph use and lattice shapes;

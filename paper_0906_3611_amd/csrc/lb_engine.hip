@@ -983,7 +983,7 @@ void engine_info(const Engine& E, lb_launch_info* out) {
   std::memset(out, 0, sizeof(*out));
   out->ntiles = E.ntiles;
   out->grid_blocks = 8 * ((E.ntiles + 7) / 8);
-  out->block_threads = lbk::kWave;
+  out->block_threads = split_kernel(E) ? 2 * lbk::kWave : lbk::kWave;
   out->workspace_bytes = E.bytes;
   size_t pb = 0;
   for (auto& mm : E.m) pb += mm.pop_bytes;

@@ -134,6 +134,7 @@ def test_launch_variants_do_not_change_fields(precision):
         lat.set_launch(seg_h=seg_h, prefetch=pf, stream_stores=nt)
         info = lat.launch_info()
         assert (info["prefetch"], info["stream_stores"]) == (pf, nt)
+        assert info["block_threads"] == (128 if precision == "fp32dev" else 64)
         lat.init(ra, rb)
         lat.step(11)
         assert np.array_equal(lat.populations(), f_ref), (seg_h, pf, nt)
