@@ -651,8 +651,8 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(independent lattices would be placed whole on separate GPUs; see DESIGN.md)",
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent lattices would be placed whole on separate GPUs)",
               file=sys.stderr)
         sys.exit(2)
     import torch
