@@ -532,7 +532,8 @@ int engine_create_dynamic(Engine& E, bool fp64, bool walls, hipStream_t stream) 
 int engine_add(Engine& E, const lb_params* p, int64_t tag, int* index) {
   std::string why;
   if (validate(p, &why) != LB_OK) return E.fail(LB_E_INVAL, why);
-  if ((p->precision == LB_FP64) != E.fp64 || (p->boundary == LB_COUETTE_Y) != E.walls)
+  if ((p->precision == LB_FP64) != E.fp64 || (p->precision == LB_FP32_MOM) != E.mom ||
+      (p->boundary == LB_COUETTE_Y) != E.walls)
     return E.fail(LB_E_INVAL, "lattice precision / boundary differ from the engine's");
   DeviceGuard dg(E.device);
   const size_t rb = member_region_bytes(p);

@@ -228,7 +228,8 @@ int lb_pool_submit_noise(lb_pool* P, const lb_params* p, uint64_t seed, double m
 int lb_pool_submit(lb_pool* P, const lb_params* p, const double* rho_a, const double* rho_b,
                    int64_t steps, int64_t* job_id) {
   if (!P || !p || !rho_a || !rho_b) return LB_E_INVAL;
-  if (p->nx < 5 || p->ny < 5) return P->fail(LB_E_INVAL, "nx and ny must be >= 5");
+  std::string why;  // the sizes must be valid before the arrays are read
+  if (lbe::validate(p, &why) != LB_OK) return P->fail(LB_E_INVAL, why);
   const size_t n = (size_t)p->nx * p->ny;
   for (size_t k = 0; k < n; ++k)
     if (!(rho_a[k] > 0) || !(rho_b[k] > 0) || !std::isfinite(rho_a[k]) || !std::isfinite(rho_b[k]))
