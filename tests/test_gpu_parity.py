@@ -304,6 +304,31 @@ def test_full_size_c2_sampled_fp64_and_fp32dev():
         lat.close()
 
 
+def test_full_size_c3_couette_sampled_fp64_and_fp32dev():
+    """C3 shape (4096 x 1024 channel, moving walls at -/+U = 0.02, noise
+    0.5 +- 0.01): 3 steps on the GPU in the benchmark's launch configuration
+    against the full oracle, fields and the wall stress averaged over the 3
+    steps (FP64 momentum exchange in both storages)."""
+    nx, ny, u = 4096, 1024, 0.02
+    ra, rb = noise(nx, ny, seed=3, amp=0.01)
+    p = oparams(nx, ny, boundary="couette", u_wall=u, **C1)
+    f, wm = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 3, avg_from=0)
+    ref = oracle.fields(p, f)
+    ref_stress = wm / 3 / nx
+    for precision, tol, stol in (("fp64", 1e-13, 1e-15), ("fp32dev", 2e-6, 1e-8)):
+        lat, _ = make(nx, ny, precision=precision, boundary="couette", u_wall=u)
+        lat.init(ra, rb)
+        lat.step(3)
+        fl = lat.fields()
+        assert np.abs(fl["rho"] - ref["rho"]).max() < tol, precision
+        assert np.abs(fl["uphys"] - ref["uphys"]).max() < tol, precision
+        obs = lat.observables()
+        assert obs["avg_count"] == 3
+        assert np.all(np.abs(obs["wall_stress"] - ref_stress) <= stol + 1e-9 * np.abs(ref_stress)), (
+            precision, obs["wall_stress"], ref_stress)
+        lat.close()
+
+
 def test_instability_is_reported():
     """A state driven far from equilibrium makes densities negative; the next
     synchronizing call reports LB_E_UNSTABLE instead of returning garbage."""
