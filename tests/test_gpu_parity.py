@@ -329,6 +329,44 @@ def test_full_size_c3_couette_sampled_fp64_and_fp32dev():
         lat.close()
 
 
+def test_full_size_c4_batch_sampled_fp32dev():
+    """C4 shape: the 256-lattice ensemble (sides log-uniform in [128, 1024],
+    67 M sites) in one batch, autotuned common segment height and graph
+    replay as the benchmark runs it, 3 steps; the smallest and the largest
+    lattice and two others against the oracle.  The sampled lattices start
+    from the input generator's disc fields, the others from the library's
+    device disc initializer."""
+    from concurrent.futures import ThreadPoolExecutor
+    lb = _lb()
+    specs = inputs.ensemble_specs(256, 4)
+    sides = [s["L"] for s in specs]
+    sample = sorted({int(np.argmin(sides)), int(np.argmax(sides)), 17, 200})
+    ps = [dict(C1, nx=s["L"], ny=s["L"], G_a=(s["G_a"], s["G_a"]), precision="fp32dev")
+          for s in specs]
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        fields = dict(zip(sample, ex.map(
+            lambda i: inputs.disc_fields(specs[i]["L"], specs[i]["L"], specs[i]["seed"],
+                                         specs[i]["phi"]), sample)))
+    b = lb.Batch(ps)
+    for i, s in enumerate(specs):
+        if i in fields:
+            b.init(i, *fields[i])
+        else:
+            b.init_discs(i, s["seed"], s["phi"])
+    b.set_launch(use_graph=1)
+    b.autotune(steps=2)
+    b.step(3)
+    for i in sample:
+        L = specs[i]["L"]
+        p = oparams(L, L, **dict(C1, G_a=ps[i]["G_a"]))
+        f, _ = oracle.run(p, oracle.init_equilibrium(p, *fields[i]), 3)
+        ref = oracle.fields(p, f)
+        got = b.fields(i)
+        assert np.abs(got["rho"] - ref["rho"]).max() < 2e-6, (i, L)
+        assert np.abs(got["uphys"] - ref["uphys"]).max() < 2e-6, (i, L)
+    b.close()
+
+
 def test_instability_is_reported():
     """A state driven far from equilibrium makes densities negative; the next
     synchronizing call reports LB_E_UNSTABLE instead of returning garbage."""
