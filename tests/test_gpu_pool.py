@@ -1,6 +1,7 @@
 """Serving pool: jobs admitted under an HBM budget and advanced together end
 exactly where the same job run alone ends (bit for bit), whatever else was
-resident; the budget is never exceeded."""
+resident; the budget is never exceeded; jobs of the serving trace's extreme
+shapes end where the FP64 oracle does, within the storage's tolerance."""
 import numpy as np
 import pytest
 import torch  # noqa: F401
@@ -84,4 +85,36 @@ def test_pool_rejects_oversized_job():
     pool.advance(10)
     assert pool.state(jid) == lb.LB_JOB_DONE
     pool.release(jid)
+    pool.close()
+
+
+def test_pool_c5_shapes_against_the_oracle():
+    """The serving trace's extreme shapes (a 2048^2 periodic job, a 64^2 and a
+    700 x 500 Couette job at U = 0.02, FP32 deviation storage), resident
+    together and advanced by the pool for a few steps: each result against
+    the FP64 oracle (densities to 2e-6; the Couette jobs' FP64 wall stress
+    averaged over their steps to 1e-8)."""
+    import oracle
+    lb = _lb()
+    jobs = [(2048, 2048, 4, "periodic"), (64, 64, 5, "couette"), (700, 500, 3, "couette")]
+    pool = lb.Pool(sum(lb.job_bytes(**dict(BASE, nx=nx, ny=ny)) for nx, ny, _, _ in jobs) * 2)
+    subs = []
+    for k, (nx, ny, steps, bnd) in enumerate(jobs):
+        u = 0.02 if bnd == "couette" else 0.0
+        sp = dict(BASE, nx=nx, ny=ny, boundary=bnd, u_wall=u)
+        ra, rb = inputs.noise_fields(nx, ny, 70 + k, 0.5, 0.5, 0.01)
+        subs.append((pool.submit(steps, ra, rb, **sp), nx, ny, steps, bnd, u, ra, rb))
+    pool.advance(max(s for _, _, s, _ in jobs))
+    assert pool.stats()["done"] == len(jobs)
+    for jid, nx, ny, steps, bnd, u, ra, rb in subs:
+        p = oracle.Params(nx=nx, ny=ny, tau=BASE["tau"], rho0=BASE["rho0"], Ga=BASE["G_a"],
+                          Gr=BASE["G_r"], Gab=BASE["G_AB"], walls=(bnd == "couette"), u_wall=u)
+        f, wm = oracle.run(p, oracle.init_equilibrium(p, ra, rb), steps, avg_from=0)
+        res = pool.result(jid)
+        assert res["obs"]["step"] == steps
+        assert np.abs(res["rho"] - oracle.fields(p, f)["rho"]).max() < 2e-6, (nx, ny)
+        if bnd == "couette":
+            ref = wm / steps / nx
+            assert np.all(np.abs(res["obs"]["wall_stress"] - ref) <= 1e-8 + 1e-9 * np.abs(ref)), (
+                nx, ny, res["obs"]["wall_stress"], ref)
     pool.close()
