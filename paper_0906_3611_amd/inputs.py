@@ -55,6 +55,21 @@ def noise_fields(nx: int, ny: int, seed: int, mean_a: float, mean_b: float, amp:
     return out[0], out[1]
 
 
+def noise_window(nx: int, ny: int, seed: int, mean_a: float, mean_b: float, amp: float,
+                 x0: int, y0: int, w: int, h: int):
+    """The (h, w) window of noise_fields(nx, ny, seed, ...) whose first site
+    is (x0, y0): rows y0 .. y0+h-1 and columns x0 .. x0+w-1, both taken
+    modulo the lattice.  The same draws, without generating the lattice."""
+    xs = ((x0 + np.arange(w)) % nx).astype(np.uint64)
+    ys = ((y0 + np.arange(h)) % ny).astype(np.uint64)
+    out = []
+    for s, mean in enumerate((mean_a, mean_b)):
+        idx = (np.uint64(s) * np.uint64(ny) + ys[:, None]) * np.uint64(nx) + xs[None, :] + np.uint64(1)
+        u = uniform01(seed, idx)
+        out.append(mean + amp * (2.0 * u - 1.0))
+    return out[0], out[1]
+
+
 def disc_mask(nx: int, ny: int, seed: int, phi: float, rmin: float = 6.0, rmax: float = 12.0,
               max_discs: int = 10_000_000) -> np.ndarray:
     """Boolean (ny, nx) mask of the union of random discs covering >= phi.

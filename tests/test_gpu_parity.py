@@ -367,6 +367,38 @@ def test_full_size_c4_batch_sampled_fp32dev():
     b.close()
 
 
+def test_maximum_size_lattice_sampled():
+    """The largest lattice the library accepts, 2^30 sites (32768^2), in FP32
+    deviation storage (two 77 GB population buffers): device noise init, 2
+    steps in the default launch.  Per-species mass against the initial mass,
+    and the densities at sampled sites (corners, edges, interior) against the
+    oracle run on the 13 x 13 periodic window around each site: two steps
+    reach 6 sites, so the window's centre evolves exactly as in the lattice."""
+    lb = _lb()
+    nx = ny = 32768
+    seed = 9
+    lat = lb.Lattice(nx, ny, precision="fp32dev", **C1)
+    lat.init_noise(seed, 0.5, 0.5, 0.01)
+    m0 = lat.observables()["mass"]
+    lat.step(2)
+    m2 = lat.observables()["mass"]
+    assert np.allclose(m2, m0, rtol=1e-7, atol=0), (m0, m2)
+    ra, rb = np.empty((ny, nx)), np.empty((ny, nx))  # densities only: 2 x 8.6 GB
+    rc = lat._lib.lb_get_fields(lat._h, lb._dptr(ra), lb._dptr(rb), lb._dptr(None), lb._dptr(None))
+    assert rc == 0, rc
+    p = oparams(13, 13, **C1)
+    for x, y in ((0, 0), (nx - 1, ny - 1), (nx - 1, 0), (3, ny // 2), (12345, 23456),
+                 (nx // 2, 6)):
+        wa, wb = inputs.noise_window(nx, ny, seed, 0.5, 0.5, 0.01, x - 6, y - 6, 13, 13)
+        f, _ = oracle.run(p, oracle.init_equilibrium(p, wa, wb), 2)
+        ref = oracle.fields(p, f)["rho"][:, 6, 6]
+        got = np.array([ra[y, x], rb[y, x]])
+        assert np.abs(got - ref).max() < 2e-6, (x, y, got, ref)
+    del ra, rb
+    lat.close()
+    torch.cuda.empty_cache()
+
+
 def test_instability_is_reported():
     """A state driven far from equilibrium makes densities negative; the next
     synchronizing call reports LB_E_UNSTABLE instead of returning garbage."""

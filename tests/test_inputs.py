@@ -29,3 +29,14 @@ def test_disc_fields_cover_requested_fraction():
     inside = a == 1.2
     assert 0.7 <= inside.mean() < 0.72
     assert np.all(b[inside] == 0.05) and np.all(a[~inside] == 0.05) and np.all(b[~inside] == 1.2)
+
+
+def test_noise_window_is_a_periodic_slice_of_the_lattice():
+    nx, ny, seed = 37, 23, 11
+    ra, rb = inputs.noise_fields(nx, ny, seed, 0.5, 0.4, 0.02)
+    for x0, y0, w, h in ((0, 0, 37, 23), (-6, -6, 13, 13), (30, 20, 13, 13), (5, 7, 3, 4)):
+        wa, wb = inputs.noise_window(nx, ny, seed, 0.5, 0.4, 0.02, x0, y0, w, h)
+        ys = (y0 + np.arange(h)) % ny
+        xs = (x0 + np.arange(w)) % nx
+        assert np.array_equal(wa, ra[np.ix_(ys, xs)])
+        assert np.array_equal(wb, rb[np.ix_(ys, xs)])
