@@ -399,6 +399,22 @@ def test_maximum_size_lattice_sampled():
     torch.cuda.empty_cache()
 
 
+def test_lattice_larger_than_the_device_is_refused():
+    """2^30 sites in FP64 storage need about 310 GB, more than the device
+    holds: creation with library-owned memory fails with LB_E_NOMEM, and the
+    device stays usable."""
+    lb = _lb()
+    with pytest.raises(lb.LBError) as ei:
+        lb.Lattice(32768, 32768, precision="fp64", use_torch=False, **C1)
+    assert ei.value.code == lb.LB_E_NOMEM
+    lat, p = make(16, 16)
+    ra, rb = noise(16, 16)
+    lat.init(ra, rb)
+    lat.step(3)
+    f, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 3)
+    assert np.abs(lat.populations() - f).max() < 1e-13
+
+
 def test_instability_is_reported():
     """A state driven far from equilibrium makes densities negative; the next
     synchronizing call reports LB_E_UNSTABLE instead of returning garbage."""
