@@ -216,7 +216,6 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
     b = lb.Batch(specs)
     for i in range(len(specs)):
         b.init_noise(i, 3 + i % realizations, 0.5, 0.5, 0.01)
-    b.set_launch(use_graph=1)
     h = curve_steps // 2
     ms = _timed(b.stream, lambda: b.step(h))
     b.reset_averages()
@@ -296,7 +295,6 @@ def bench_kolmogorov(speeds=(0.005, 0.01, 0.02, 0.03, 0.04, 0.05), n=128,
     ra, rb = inputs.noise_fields(n, n, seed, 0.612, 0.612, 0.01)
     for i in range(len(speeds)):
         b.init(i, ra, rb)
-    b.set_launch(use_graph=1)
     tuned = b.autotune(steps=20)
     rows, done, ms = [], 0, 0.0
     for t in checkpoints:
@@ -328,7 +326,6 @@ def bench_ensemble(n_real=100, n=128, U0=0.02, steps=100000, every=10000, t_w=20
     for i in range(n_real):
         ra, rb = inputs.noise_fields(n, n, seed0 + i, 0.612, 0.612, 0.01)
         b.init(i, ra, rb)
-    b.set_launch(use_graph=1)
     b.autotune(steps=20)
 
     def phi_all():
@@ -358,9 +355,12 @@ def bench_batch(n=256, steps=5000, seed=4, tune_steps=10):
     """Ensemble of n independent square lattices (sides log-uniform in
     [128, 1024], G^a in [-9.5, -8.5], disc fraction in [0.5, 0.8]) in FP32
     storage: all of them advanced by one launch per step (autotuned common
-    tile height, graph replay) versus the same kernels one lattice at a time,
-    each lattice with its own autotuned launch shape and graph replay.  Every
-    lattice's density fields must agree bit for bit between the two."""
+    tile height, graph replay as the workload prescribes; the same batch with
+    plain launches is timed afterwards) versus the same kernels one lattice at
+    a time, each lattice with its own autotuned launch shape and plain
+    launches (graph replay measured 2.3-4 us per step slower for single
+    lattices of these sizes).  Every lattice's density fields must agree bit
+    for bit between the two."""
     from concurrent.futures import ThreadPoolExecutor
     import numpy as np
     from paper_0906_3611_amd import inputs, lb
@@ -388,14 +388,18 @@ def bench_batch(n=256, steps=5000, seed=4, tune_steps=10):
         nx, ny = kw.pop("nx"), kw.pop("ny")
         lat = lb.Lattice(nx, ny, **kw)
         lat.init(ra, rb)
-        lat.set_launch(use_graph=1)
         lat.autotune(steps=tune_steps)
         ms_seq += _timed(lat.stream, lambda: lat.step(steps))
         if not np.array_equal(lat.fields()["rho"], b.fields(i)["rho"]):
             mismatched.append(i)
         lat.close()
     wall_seq = time.perf_counter() - t0
+    # the batch again with plain launches (state continues; nothing compared)
+    b.set_launch(use_graph=0)
+    plain_steps = max(2, steps // 10)
+    ms_plain = _timed(b.stream, lambda: b.step(plain_steps))
     b.close()
+    plain_mlups = sites * plain_steps / (ms_plain * 1e-3) / 1e6
     seq_mlups = sites * steps / (ms_seq * 1e-3) / 1e6
     print(f"# one at a time: {seq_mlups:.0f} MLUPS", file=sys.stderr, flush=True)
     return {"workload": f"{n} square lattices, sides log-uniform in [128, 1024] (seed {seed}), "
@@ -403,6 +407,7 @@ def bench_batch(n=256, steps=5000, seed=4, tune_steps=10):
             "sites": sites, "value": batch_mlups, "ms_per_step": ms_b / steps,
             "batch_launch": {k: tuned[k] for k in ("seg_h", "ntiles", "prefetch", "stream_stores",
                                                    "use_graph", "us_per_step")},
+            "batch_plain_launches": {"value": plain_mlups, "steps": plain_steps},
             "one_at_a_time": {"value": seq_mlups, "gpu_ms": ms_seq, "wall_s": wall_seq},
             "speedup": batch_mlups / seq_mlups,
             "fields_bitwise_equal": not mismatched, "mismatched": mismatched[:8],
@@ -428,7 +433,7 @@ def replay_trace(trace, budget_bytes, tick_s=0.02):
     arrival to the moment its observables and density fields are on the
     host (the pool's clock)."""
     from paper_0906_3611_amd import lb
-    pool = lb.Pool(budget_bytes, keep_fields=True, use_graph=True)
+    pool = lb.Pool(budget_bytes, keep_fields=True)
     c0 = pool.stats()["clock"]
     t0 = time.perf_counter()
     pending = list(trace)

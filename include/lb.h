@@ -210,7 +210,10 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
  *   prefetch: rows whose loads are in flight ahead of the current one
  *     (0, 1 or 2; larger values mean 2; the moment storage ignores it).
  *   stream_stores: nontemporal population stores.
- *   use_graph: replay lb_step as captured two-step HIP graphs. */
+ *   use_graph: replay lb_step as captured two-step HIP graphs (default 0:
+ *     on MI355X under ROCm 7 a replayed step measured 2.3-2.5 us longer than
+ *     a plain launch of the same kernel, so graphs only pay where the caller's
+ *     host-side launch rate is the limit). */
 int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
                   int32_t use_graph);
 
@@ -308,7 +311,8 @@ int lb_pool_create(size_t hbm_budget_bytes, void* hip_stream, lb_pool** out);
 void lb_pool_destroy(lb_pool* pool);
 const char* lb_pool_last_error(const lb_pool* pool);
 /* keep_fields: copy final densities at retirement (default 1); use_graph:
- * replay step pairs as HIP graphs (default 1).  < 0 keeps the setting. */
+ * replay step pairs as HIP graphs (default 0, see lb_set_launch).  < 0 keeps
+ * the setting. */
 int lb_pool_set_options(lb_pool* pool, int32_t keep_fields, int32_t use_graph);
 /* Device footprint of one job with these parameters (0 if invalid). */
 size_t lb_pool_job_bytes(const lb_params* p);

@@ -58,7 +58,7 @@ struct lb_pool {
   int64_t next_id = 1;
   int64_t site_updates = 0, ticks = 0, steps_run = 0;
   int keep_fields = 1;
-  int use_graph = 1;
+  int use_graph = 0;
   Clock::time_point t0 = Clock::now();
   std::string err;
 

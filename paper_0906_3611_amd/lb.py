@@ -491,7 +491,7 @@ class Pool(_Handle):
     _destroy = "lb_pool_destroy"
     _last_error = "lb_pool_last_error"
 
-    def __init__(self, budget_bytes, stream=None, keep_fields=True, use_graph=True):
+    def __init__(self, budget_bytes, stream=None, keep_fields=True, use_graph=False):
         self._lib = load()
         _load_pool_symbols(self._lib)
         self._h = ctypes.c_void_p()

@@ -40,14 +40,14 @@ def _alone(sp, steps, seed):
     return lat.fields()["rho"], lat.observables()
 
 
-@pytest.mark.parametrize("budget_frac", [1.0, 0.3])
-def test_pool_results_match_lone_runs(budget_frac):
+@pytest.mark.parametrize("budget_frac,use_graph", [(1.0, False), (0.3, False), (0.3, True)])
+def test_pool_results_match_lone_runs(budget_frac, use_graph):
     lb = _lb()
     jobs = _jobs()
     total = sum(lb.job_bytes(**sp) for sp, _, _ in jobs)
     biggest = max(lb.job_bytes(**sp) for sp, _, _ in jobs)
     budget = max(int(total * budget_frac), biggest)
-    pool = lb.Pool(budget)
+    pool = lb.Pool(budget, use_graph=use_graph)
     ids = []
     for sp, steps, seed in jobs:
         ra, rb = inputs.noise_fields(sp["nx"], sp["ny"], seed, 0.5, 0.5, 0.05)
