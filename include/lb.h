@@ -219,7 +219,7 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
 
 /* Autotuner: time candidate launch shapes on the lattice's current state and
  * keep the fastest.  Candidates are the default policy and forced segment
- * heights of 8 to 256 rows with the current code variant, then the six
+ * heights of 4 to 256 rows with the current code variant, then the six
  * prefetch (0..2) / stream_stores variants at the best height (the moment
  * storage has no prefetch variants: only its two stream_stores variants are
  * timed there); each runs 2 untimed

@@ -28,8 +28,11 @@ bool is_finite(double v) { return std::isfinite(v); }
 
 // Default tile policy (measured): FP32 kernels fit 2-3 waves per SIMD, FP64
 // ones 1, so FP32 aims at ~2048 wavefronts with 32-row segments and FP64 at
-// ~1024 with 64-row segments; segments get shorter (down to 8 rows) only to
-// reach that many tiles.
+// ~1024 with 64-row segments; segments get shorter (down to 4 rows) only to
+// reach that many tiles.  A lattice too small to fill the GPU is bound by the
+// latency of one tile's march, which 4-row segments cut from 12 to 8 rows:
+// at 128^2 a step takes 10.1 us against 14.7 with 8-row segments (FP64 17.3
+// against 26.7), at 512^2 14.0 against 18.6.
 int target_tiles(const lb_params* p) { return p->precision == LB_FP64 ? 1024 : 2048; }
 int base_seg_h(const lb_params* p) { return p->precision == LB_FP64 ? 64 : 32; }
 
@@ -44,7 +47,7 @@ lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   g.nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
   const int h0 = base_seg_h(p);
   int nsegs = std::max((p->ny + h0 - 1) / h0, (target_tiles(p) + g.nstrips - 1) / g.nstrips);
-  nsegs = std::min(nsegs, std::max(1, p->ny / 8));
+  nsegs = std::min(nsegs, std::max(1, p->ny / 4));
   if (seg_h >= 4) nsegs = (p->ny + seg_h - 1) / seg_h;
   nsegs = std::max(1, std::min(nsegs, p->ny));
   g.nsegs = nsegs;
@@ -222,15 +225,15 @@ void choose_default_variant(Engine& E);
 
 // Member geometries.  A forced height applies to every member.  Otherwise a
 // single lattice uses make_geometry's policy, and several lattices share one
-// segment height: base_seg_h, halved (down to 8) only while the engine's
+// segment height: base_seg_h, halved (down to 4) only while the engine's
 // tiles stay under target_tiles, so that small members are not cut into
-// 8-row segments when the whole launch has tiles to spare.
+// short segments when the whole launch has tiles to spare.
 std::vector<lbk::Geometry> geometries(const Engine& E, int seg_h) {
   std::vector<lbk::Geometry> g;
   int h = seg_h;
   if (seg_h < 4 && E.m.size() > 1) {
     const lb_params* p0 = &E.m[0].p;  // members share the precision
-    for (h = base_seg_h(p0); h > 8; h /= 2) {
+    for (h = base_seg_h(p0); h > 4; h /= 2) {
       long long tiles = 0;
       for (auto& mm : E.m) tiles += (long long)make_geometry(&mm.p, h).ntiles;
       if (tiles >= target_tiles(p0)) break;
@@ -920,7 +923,7 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   int ny_max = 0;
   for (auto& mm : E.m) ny_max = std::max(ny_max, mm.p.ny);
   std::vector<int> heights = {0};
-  for (int h : {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+  for (int h : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
     if (h < ny_max + 8) heights.push_back(h);
   std::vector<std::vector<int>> seen;
   int best_h = seg0;
