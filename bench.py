@@ -439,8 +439,13 @@ def replay_trace(trace, budget_bytes, tick_s=0.02):
     pending = list(trace)
     live, lat = {}, []
     n_adv = 8
+    t_report = time.perf_counter()
     while pending or live:
         now = time.perf_counter() - t0
+        if time.perf_counter() - t_report > 30.0:
+            print(f"# serving: {len(lat)}/{len(trace)} jobs done at {now:.0f} s", file=sys.stderr,
+                  flush=True)
+            t_report = time.perf_counter()
         while pending and pending[0]["t"] <= now:
             j = pending.pop(0)
             jid = pool.submit_noise(j["steps"], j["seed"], 0.5, 0.5, 0.01, **_job_spec(j, "fp32dev"))
@@ -481,7 +486,11 @@ def service_times(trace, precision, timed_steps=100):
     plus the measured initialization and result transfer of that lattice."""
     from paper_0906_3611_amd import lb
     cache, out = {}, []
-    for j in trace:
+    t_report = time.perf_counter()
+    for k, j in enumerate(trace):
+        if time.perf_counter() - t_report > 30.0:
+            print(f"# {precision} service times: {k}/{len(trace)} jobs", file=sys.stderr, flush=True)
+            t_report = time.perf_counter()
         key = (j["L"], j["boundary"], j["u_wall"])
         if key not in cache:
             kw = _job_spec(j, precision)
