@@ -206,7 +206,8 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
 /* Tuning knobs that leave the arithmetic unchanged: fields and observables
  * stay bit for bit the same (the FP64 reductions run over (row, strip) and
  * strip partials, not over tiles).  Any argument < 0 keeps the current choice.
- *   seg_h: row-segment height (0 = default policy); wall averages carry on.
+ *   seg_h: row-segment height, >= 4 (0 to 3 = default policy); wall
+ *     averages carry on.
  *   prefetch: rows whose loads are in flight ahead of the current one
  *     (0, 1 or 2; larger values mean 2; the moment storage ignores it).
  *   stream_stores: nontemporal population stores.
