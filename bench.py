@@ -617,6 +617,22 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
     print(json.dumps(rec[f"{precision}@{sites}"]))
 
 
+def device_copy_gbs(nbytes: int, reps: int = 20) -> float:
+    """Rate of a plain device-to-device copy (torch) that reads and writes
+    nbytes / 2 each, in GB/s of bytes read plus written: what this GPU moves
+    for a streaming pattern of the same size, as context for a kernel's
+    achieved rate."""
+    import torch
+    n = max(1, nbytes // 8)  # float32 elements per direction
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = _timed(torch.cuda.current_stream(), lambda: [b.copy_(a) for _ in range(reps)]) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 8.0 * n / (ms * 1e-3) / 1e9
+
+
 def copy_probe(mib: int = 1024, reps: int = 5):
     """A plain device copy of known size (for counter calibration)."""
     import torch
@@ -706,16 +722,22 @@ def main():
         # than the 256 MB Infinity Cache, unlike the 1024^2 workload.
         pa, pb = inputs.noise_fields(4096, 1024, 3, 0.5, 0.5, 0.01)
         pr = run_gpu(4096, 1024, args.precision, 2000, 100, pa, pb)
+        cp = device_copy_gbs(BYTES_PER_SITE[args.precision] * 4096 * 1024)
         extra["hbm_probe_4096x1024"] = {"value": pr["mlups"], "ms_per_step": pr["ms_per_step"],
                                         "achieved_gbs": pr["achieved_gbs"],
-                                        "frac": pr["achieved_gbs"] / PEAK_HBM_GBS}
+                                        "frac": pr["achieved_gbs"] / PEAK_HBM_GBS,
+                                        "device_copy_gbs": cp,
+                                        "frac_of_device_copy": pr["achieved_gbs"] / cp}
         print(f"# probe 4096x1024: {pr['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         # 4096^2 (2.4 GB of FP32 populations)
         qa, qb = inputs.noise_fields(4096, 4096, 3, 0.5, 0.5, 0.01)
         pq = run_gpu(4096, 4096, args.precision, 400, 20, qa, qb)
+        cq = device_copy_gbs(BYTES_PER_SITE[args.precision] * 4096 * 4096)
         extra["hbm_probe_4096x4096"] = {"value": pq["mlups"], "ms_per_step": pq["ms_per_step"],
                                         "achieved_gbs": pq["achieved_gbs"],
-                                        "frac": pq["achieved_gbs"] / PEAK_HBM_GBS}
+                                        "frac": pq["achieved_gbs"] / PEAK_HBM_GBS,
+                                        "device_copy_gbs": cq,
+                                        "frac_of_device_copy": pq["achieved_gbs"] / cq}
         print(f"# probe 4096x4096: {pq['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
     if not args.no_moment and args.precision != "fp32mom":
