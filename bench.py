@@ -774,6 +774,9 @@ def main():
             "units_per_launch": sites,
             # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed
             "cache_resident": pop_bytes <= (256 << 20)}
+    # context: a plain device copy of the same bytes on this GPU
+    roof["device_copy_gbs"] = device_copy_gbs(pop_bytes)
+    roof["frac_of_device_copy"] = main_run["achieved_gbs"] / roof["device_copy_gbs"]
     line = {
         "metric": "two-species MLUPS",
         "value": main_run["mlups"],
