@@ -26,13 +26,19 @@ constexpr size_t kInfinityCacheBytes = 256ull << 20;
 
 bool is_finite(double v) { return std::isfinite(v); }
 
-// Default tile policy (measured): FP32 kernels fit 2-3 waves per SIMD, FP64
-// ones 1, so FP32 aims at ~2048 wavefronts with 32-row segments and FP64 at
-// ~1024 with 64-row segments; segments get shorter (down to 4 rows) only to
-// reach that many tiles.  A lattice too small to fill the GPU is bound by the
-// latency of one tile's march, which 4-row segments cut from 12 to 8 rows:
-// at 128^2 a step takes 10.1 us against 14.7 with 8-row segments (FP64 17.3
-// against 26.7), at 512^2 14.0 against 18.6.
+// Default tile policy (measured).  The population kernels run fastest with
+// about one wave of resident workgroups: ~2048 tiles for FP32 (k_split,
+// two-wave workgroups, ~10 per CU) and ~1024 for FP64 (k_march, one wave
+// per SIMD), whatever height that gives: at 4096^2 128-row segments beat
+// 32-row ones by 2% periodic and 9% with walls (more tiles than fit at once
+// lose the L2 reuse of the halo rows between segments: 1.21x the
+// algorithmic reads at 32 rows).  The moment kernel, bound by instruction
+// issue, prefers more tiles: segments of at most base_seg_h rows (4096^2:
+// 66.0 G site updates/s at 32 rows, 60.3 at 128).  Segments get shorter
+// (down to 4 rows) only to reach the tile count: a lattice too small to fill
+// the GPU is bound by the latency of one tile's march, which 4-row segments
+// cut from 12 to 8 rows (128^2: 10.1 us per step against 14.7 with 8-row
+// segments, FP64 17.3 against 26.7; 512^2: 14.0 against 18.6).
 int target_tiles(const lb_params* p) { return p->precision == LB_FP64 ? 1024 : 2048; }
 int base_seg_h(const lb_params* p) { return p->precision == LB_FP64 ? 64 : 32; }
 
@@ -45,8 +51,11 @@ lbk::Geometry make_geometry(const lb_params* p, int seg_h) {
   g.pitch = (p->nx + lbk::kWave - 1) / lbk::kWave * lbk::kWave;  // strips start on a line
   g.row_elems = (long long)(g.pitch / lbk::kWave) * (p->precision == LB_FP32_MOM ? 6 : 18) * lbk::kWave;
   g.nstrips = (p->nx + lbk::kWave - 1) / lbk::kWave;
-  const int h0 = base_seg_h(p);
-  int nsegs = std::max((p->ny + h0 - 1) / h0, (target_tiles(p) + g.nstrips - 1) / g.nstrips);
+  int nsegs = (target_tiles(p) + g.nstrips - 1) / g.nstrips;
+  if (p->precision == LB_FP32_MOM) {
+    const int h0 = base_seg_h(p);
+    nsegs = std::max(nsegs, (p->ny + h0 - 1) / h0);
+  }
   nsegs = std::min(nsegs, std::max(1, p->ny / 4));
   if (seg_h >= 4) nsegs = (p->ny + seg_h - 1) / seg_h;
   nsegs = std::max(1, std::min(nsegs, p->ny));
