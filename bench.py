@@ -727,7 +727,8 @@ def main():
                                         "achieved_gbs": pr["achieved_gbs"],
                                         "frac": pr["achieved_gbs"] / PEAK_HBM_GBS,
                                         "device_copy_gbs": cp,
-                                        "frac_of_device_copy": pr["achieved_gbs"] / cp}
+                                        "frac_of_device_copy": pr["achieved_gbs"] / cp,
+                                        "traffic": traffic_for(args.precision, 4096 * 1024)}
         print(f"# probe 4096x1024: {pr['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         # 4096^2 (2.4 GB of FP32 populations)
         qa, qb = inputs.noise_fields(4096, 4096, 3, 0.5, 0.5, 0.01)
@@ -737,7 +738,8 @@ def main():
                                         "achieved_gbs": pq["achieved_gbs"],
                                         "frac": pq["achieved_gbs"] / PEAK_HBM_GBS,
                                         "device_copy_gbs": cq,
-                                        "frac_of_device_copy": pq["achieved_gbs"] / cq}
+                                        "frac_of_device_copy": pq["achieved_gbs"] / cq,
+                                        "traffic": traffic_for(args.precision, 4096 * 4096)}
         print(f"# probe 4096x4096: {pq['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
 
     if not args.no_moment and args.precision != "fp32mom":
