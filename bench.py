@@ -741,6 +741,15 @@ def main():
                                         "frac_of_device_copy": pq["achieved_gbs"] / cq,
                                         "traffic": traffic_for(args.precision, 4096 * 4096)}
         print(f"# probe 4096x4096: {pq['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        # one GPU's share of a y-slab decomposition of a 4096-wide channel over 8
+        # GPUs: 128 owned rows plus the 3 ghost rows per side a step would need
+        sa, sb = inputs.noise_fields(4096, 134, 3, 0.5, 0.5, 0.01)
+        ps = run_gpu(4096, 134, args.precision, 4000, 200, sa, sb)
+        extra["slab_share_4096x134"] = {"value": ps["mlups"], "us_per_step": ps["ms_per_step"] * 1e3,
+                                        "owned_rows": 128, "ghost_rows_per_side": 3,
+                                        "achieved_gbs": ps["achieved_gbs"]}
+        print(f"# slab share 4096x134: {ps['ms_per_step'] * 1e3:.1f} us/step", file=sys.stderr,
+              flush=True)
 
     if not args.no_moment and args.precision != "fp32mom":
         extra["moment_tau1"] = bench_moment(nx, ny, args.steps, args.warmup, rho_a, rho_b,
