@@ -185,8 +185,8 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
     """Planar Couette channel 4096 x 1024 (walls on y, periodic x) in FP32
     storage: throughput over `steps` steps per wall speed, wall stress
     averaged over the second half.  Then the reduced stress-vs-shear-rate
-    curve on a 512 x 128 channel (one batch of the three speeds, graph
-    replay), averaged over the second half of `curve_steps` steps."""
+    curve on a 512 x 128 channel (one batch of the three speeds, plain
+    launches), averaged over the second half of `curve_steps` steps."""
     from paper_0906_3611_amd import inputs, lb
     nx, ny = 4096, 1024
     ra, rb = inputs.noise_fields(nx, ny, 3, 0.5, 0.5, 0.01)
@@ -285,7 +285,7 @@ def bench_kolmogorov(speeds=(0.005, 0.01, 0.02, 0.03, 0.04, 0.05), n=128,
     """The shear protocol of Sec. VIII (Figs. 10, 11): 128^2 periodic, the
     standard rho0 = 0.7 couplings, <rho_A> = <rho_B> = 0.612 +- 0.01, tau = 1,
     body force driving U_x = U0 sin(2 pi y / n), one lattice per U0 in one
-    batch (graph replay, autotuned).  Reports the response R = u_mode / U0
+    batch (plain launches, autotuned).  Reports the response R = u_mode / U0
     (Eq. (66)) and the interface indicator I_AB (Eq. (67)) at each checkpoint."""
     from paper_0906_3611_amd import inputs, lb
     par = dict(tau=(1.0, 1.0), rho0=0.7, G_a=(-15.0, -14.0), G_r=(14.1, 13.1), G_AB=0.405)
