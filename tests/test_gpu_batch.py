@@ -263,3 +263,23 @@ def test_observables_do_not_depend_on_segment_height(precision):
     for k in ("mass", "mom", "mom_phys", "wall_stress"):
         assert np.array_equal(oa[k], ob[k]), k
     assert oa["pxy_kin"] == ob["pxy_kin"] and oa["avg_count"] == ob["avg_count"] == 13
+
+
+@pytest.mark.parametrize("precision,nx,ny,seg_h", [
+    ("fp32dev", 1024, 1024, 8),     # ~2048 tiles: one wave of resident workgroups
+    ("fp32dev", 4096, 1024, 32),
+    ("fp32dev", 4096, 4096, 128),   # taller segments keep the halo rows in L2
+    ("fp32dev", 128, 128, 4),       # too small to fill the GPU: shortest march
+    ("fp64", 1024, 1024, 16),       # ~1024 tiles
+    ("fp64", 4096, 4096, 256),
+    ("fp32mom", 4096, 4096, 32),    # issue-bound: at most 32-row segments
+    ("fp32mom", 128, 128, 4),
+])
+def test_default_tile_policy(precision, nx, ny, seg_h):
+    """The default launch shapes are the measured best ones (see the policy
+    in lb_engine.hip); a change of the policy shows up here."""
+    lat = _lb().Lattice(nx, ny, precision=precision, **BASE)
+    info = lat.launch_info()
+    assert info["seg_h"] == seg_h, info
+    assert info["ntiles"] == info["nstrips"] * info["nsegs"]
+    lat.close()
