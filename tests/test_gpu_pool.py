@@ -20,11 +20,16 @@ def _lb():
 
 
 def _jobs():
+    """Jobs of all four (precision, boundary) classes the pool keeps engines
+    for, of uneven sizes and step counts (one with no steps)."""
     out = []
-    for k, (nx, ny, steps, bnd) in enumerate(((64, 64, 40, "periodic"), (130, 70, 25, "couette"),
-                                                (96, 40, 60, "periodic"), (70, 33, 7, "couette"),
-                                                (200, 120, 33, "periodic"), (64, 64, 0, "periodic"))):
-        sp = dict(BASE, nx=nx, ny=ny, boundary=bnd, u_wall=0.01 if bnd == "couette" else 0.0)
+    for k, (nx, ny, steps, bnd, prec) in enumerate((
+            (64, 64, 40, "periodic", "fp32dev"), (130, 70, 25, "couette", "fp32dev"),
+            (96, 40, 60, "periodic", "fp32dev"), (70, 33, 7, "couette", "fp32dev"),
+            (200, 120, 33, "periodic", "fp32dev"), (64, 64, 0, "periodic", "fp32dev"),
+            (90, 45, 17, "periodic", "fp64"), (66, 50, 29, "couette", "fp64"))):
+        sp = dict(BASE, nx=nx, ny=ny, boundary=bnd, u_wall=0.01 if bnd == "couette" else 0.0,
+                  precision=prec)
         out.append((sp, steps, 50 + k))
     return out
 
