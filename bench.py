@@ -426,14 +426,16 @@ def _job_spec(j, precision):
                 u_wall=j["u_wall"])
 
 
-def replay_trace(trace, budget_bytes, tick_s=0.02):
+def replay_trace(trace, budget_bytes, tick_s=0.02, schedule="srpt", fill_sites=0):
     """Replays an arrival trace in real time against a serving pool: each job
     is submitted when its arrival time has passed, the pool is advanced in
     ticks of about tick_s seconds, and a job's time-to-result runs from its
     arrival to the moment its observables and density fields are on the
-    host (the pool's clock)."""
+    host (the pool's clock).  schedule: the pool's ("srpt": least remaining
+    work advances first, up to fill_sites sites, 0 for the pool's default;
+    "lockstep": every resident job every step)."""
     from paper_0906_3611_amd import lb
-    pool = lb.Pool(budget_bytes, keep_fields=True)
+    pool = lb.Pool(budget_bytes, keep_fields=True, schedule=schedule, fill_sites=fill_sites)
     c0 = pool.stats()["clock"]
     t0 = time.perf_counter()
     pending = list(trace)
@@ -474,9 +476,9 @@ def replay_trace(trace, budget_bytes, tick_s=0.02):
     work = sum(j["L"] ** 2 * j["steps"] for j in trace)
     st = pool.stats()
     pool.close()
-    return {"jobs": len(trace), "latency_s": _percentiles(lat), "makespan_s": makespan,
-            "value": work / makespan / 1e6, "site_updates": work, "budget_bytes": budget_bytes,
-            "pool_ticks": st["ticks"]}
+    return {"jobs": len(trace), "schedule": schedule, "latency_s": _percentiles(lat),
+            "makespan_s": makespan, "value": work / makespan / 1e6, "site_updates": work,
+            "budget_bytes": budget_bytes, "pool_ticks": st["ticks"]}
 
 
 def service_times(trace, precision, timed_steps=100):
@@ -526,7 +528,8 @@ def fifo(trace, service):
 def bench_serving(n_jobs=60, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5):
     """Serving trace (Poisson arrivals, half Couette / half periodic, sides
     log-uniform in [64, 2048], steps log-uniform in [1e3, 5e4], FP32 storage)
-    replayed in real time against the pool, then a rate-scaled variant at 0.7
+    replayed in real time against the pool (least-remaining-work schedule,
+    then again lock-step), then a rate-scaled variant at 0.7
     of the capacity measured in the first replay.  Baselines: a sequential
     first-in first-out server running one job at a time on the same GPU, in
     FP64 and in FP32 storage, simulated from per-job service times measured
@@ -540,9 +543,14 @@ def bench_serving(n_jobs=60, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5):
           file=sys.stderr, flush=True)
     out = {"workload": f"{n_jobs} Poisson arrivals at {rate}/s (seed {seed}), 50/50 Couette/periodic, "
                        f"sides 64-2048, 1e3-5e4 steps, fp32dev, HBM budget {budget_gb} GiB",
-           "served": served,
+           "served": served}
+    lock = replay_trace(tr, budget, schedule="lockstep")
+    print(f"# same trace, lock-step pool: {lock['value']:.0f} MLUPS, "
+          f"p50 {lock['latency_s']['p50']:.2f} s p99 {lock['latency_s']['p99']:.2f} s",
+          file=sys.stderr, flush=True)
+    out.update({"served_lockstep": lock,
            "fifo_fp64": fifo(tr, service_times(tr, "fp64")),
-           "fifo_fp32dev": fifo(tr, service_times(tr, "fp32dev"))}
+           "fifo_fp32dev": fifo(tr, service_times(tr, "fp32dev"))})
     if n_scaled:
         mean_work = sum(j["L"] ** 2 * j["steps"] for j in tr) / len(tr)
         cap_rate = served["value"] * 1e6 / mean_work  # jobs/s at the measured throughput

@@ -57,6 +57,9 @@ struct Engine {
   int seg_h = 0;              // forced segment height of every member (0: per-lattice default)
   bool use_graph = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two-step graphs by starting parity
+  // device tables of the last subset launch (engine_step_subset)
+  char* sub = nullptr;
+  size_t sub_bytes = 0;
   std::string err;
 
   int fail(int code, const std::string& msg) {
@@ -88,6 +91,10 @@ int engine_init(Engine& E, int i, const double* rho_a, const double* rho_b, cons
                 const double* uy);
 int engine_init_noise(Engine& E, int i, uint64_t seed, double mean_a, double mean_b, double amp);
 int engine_step(Engine& E, int64_t n);
+// Advance only the members sel[] (distinct indices) by n steps; the others
+// keep their state, time and wall averages as if the engine had not
+// stepped.  Population storages only (LB_E_INVAL for the moment storage).
+int engine_step_subset(Engine& E, const std::vector<int>& sel, int64_t n);
 int engine_observables(Engine& E, lb_obs* out /*[members]*/);
 int engine_member_observables(Engine& E, int i, lb_obs* out);
 int engine_fields(Engine& E, int i, double* rho_a, double* rho_b, double* u, double* u_phys);

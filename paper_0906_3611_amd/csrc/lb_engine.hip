@@ -237,18 +237,27 @@ void choose_default_variant(Engine& E);
 // segment height: base_seg_h, halved (down to 4) only while the engine's
 // tiles stay under target_tiles, so that small members are not cut into
 // short segments when the whole launch has tiles to spare.
-std::vector<lbk::Geometry> geometries(const Engine& E, int seg_h) {
+// The storage layout does not depend on the segment height, so a launch
+// over some of the members may tile them as if they were alone (sel: member
+// indices; null: every member).
+std::vector<lbk::Geometry> geometries(const Engine& E, int seg_h,
+                                      const std::vector<int>* sel = nullptr) {
+  std::vector<const lb_params*> ps;
+  if (sel)
+    for (int i : *sel) ps.push_back(&E.m[i].p);
+  else
+    for (auto& mm : E.m) ps.push_back(&mm.p);
   std::vector<lbk::Geometry> g;
   int h = seg_h;
-  if (seg_h < 4 && E.m.size() > 1) {
-    const lb_params* p0 = &E.m[0].p;  // members share the precision
+  if (seg_h < 4 && ps.size() > 1) {
+    const lb_params* p0 = ps[0];  // members share the precision
     for (h = base_seg_h(p0); h > 4; h /= 2) {
       long long tiles = 0;
-      for (auto& mm : E.m) tiles += (long long)make_geometry(&mm.p, h).ntiles;
+      for (auto* p : ps) tiles += (long long)make_geometry(p, h).ntiles;
       if (tiles >= target_tiles(p0)) break;
     }
   }
-  for (auto& mm : E.m) g.push_back(make_geometry(&mm.p, h));
+  for (auto* p : ps) g.push_back(make_geometry(p, h));
   return g;
 }
 
@@ -592,8 +601,11 @@ void engine_destroy(Engine& E) {
   E.m.clear();
   if (E.owns_shared && E.shared) (void)hipFree(E.shared);
   if (E.owns_block && E.block) (void)hipFree(E.block);
+  if (E.sub) (void)hipFree(E.sub);
   E.shared = nullptr;
   E.block = nullptr;
+  E.sub = nullptr;
+  E.sub_bytes = 0;
 }
 
 int engine_init(Engine& E, int i, const double* rho_a, const double* rho_b, const double* ux,
@@ -670,6 +682,82 @@ int engine_step(Engine& E, int64_t n) {
   if (E.mom && n > 0)
     for (auto& mm : E.m) mm.d.local[0] = mm.d.local[1] = 0;
   return LB_OK;
+}
+
+// Each launch runs over the selected members' tiles only, through a
+// descriptor array and tile map of their own (copies of the members'
+// records, tiled as if the selected members were the whole engine, tile
+// bases renumbered from 0), so the kernels are those of a whole-engine
+// step.  A member left out of n steps keeps its buffers; its
+// buffer phase and time bases move by n, so that the engine's parity still
+// selects its current buffer and its time and wall averages count only its
+// own steps.
+int engine_step_subset(Engine& E, const std::vector<int>& sel, int64_t n) {
+  if (n < 0) return E.fail(LB_E_INVAL, "n must be >= 0");
+  if (E.mom) return E.fail(LB_E_INVAL, "subset steps need population storage");
+  std::vector<char> in(E.m.size(), 0);
+  for (int i : sel) {
+    if (i < 0 || i >= (int)E.m.size() || in[i])
+      return E.fail(LB_E_INVAL, "subset indices out of range or repeated");
+    if (!E.m[i].initialized) return E.fail(LB_E_STATE, "step before every lattice is initialized");
+    in[i] = 1;
+  }
+  if (sel.empty() || n == 0) return LB_OK;
+  if (sel.size() == E.m.size()) return engine_step(E, n);
+  DeviceGuard dg(E.device);
+  const auto geo = geometries(E, E.seg_h, &sel);
+  std::vector<lbk::LatticeDesc> d;
+  std::vector<int> map;
+  int base = 0;
+  for (int k = 0; k < (int)sel.size(); ++k) {
+    lbk::LatticeDesc x = E.m[sel[k]].d;
+    x.g = geo[k];
+    x.tile_base = base;
+    base += x.g.ntiles;
+    map.insert(map.end(), x.g.ntiles, k);
+    d.push_back(x);
+  }
+  const size_t bd = align_up(d.size() * sizeof(lbk::LatticeDesc));
+  const size_t need = bd + align_up(map.size() * sizeof(int));
+  if (E.sub_bytes < need) {
+    HIPCK(E, hipStreamSynchronize(E.stream));  // the old tables may still be read
+    if (E.sub) (void)hipFree(E.sub);
+    E.bytes -= E.sub_bytes;
+    E.sub = nullptr;
+    E.sub_bytes = 0;
+    void* b = nullptr;
+    if (hipMalloc(&b, need) != hipSuccess) {
+      (void)hipGetLastError();
+      return E.fail(LB_E_NOMEM, "hipMalloc of the subset tables failed");
+    }
+    E.sub = (char*)b;
+    E.sub_bytes = need;
+    E.bytes += need;
+  }
+  HIPCK(E, hipMemcpyAsync(E.sub, d.data(), d.size() * sizeof(lbk::LatticeDesc),
+                          hipMemcpyHostToDevice, E.stream));
+  HIPCK(E, hipMemcpyAsync(E.sub + bd, map.data(), map.size() * sizeof(int), hipMemcpyHostToDevice,
+                          E.stream));
+  HIPCK(E, hipStreamSynchronize(E.stream));  // the host vectors die at return
+  lbk::LaunchArgs a{};
+  a.descs = (const lbk::LatticeDesc*)E.sub;
+  a.tile_lattice = (const int*)(E.sub + bd);
+  a.ntiles = base;
+  a.tiles_per_xcd = (base + 7) / 8;
+  a.accumulate_wall = E.walls ? 1 : 0;
+  for (int64_t k = 0; k < n; ++k) {
+    a.parity = (int)(E.step & 1);
+    HIPCK(E, step_launch(E, a, E.stream));
+    ++E.step;
+  }
+  for (size_t i = 0; i < E.m.size(); ++i) {
+    if (in[i]) continue;
+    Member& mm = E.m[i];
+    mm.d.phase ^= (int)(n & 1);
+    mm.e_base += n;
+    mm.avg_start += n;
+  }
+  return upload_descs(E);
 }
 
 int engine_observables(Engine& E, lb_obs* out /*[n]*/) {

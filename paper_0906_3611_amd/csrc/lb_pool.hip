@@ -59,6 +59,13 @@ struct lb_pool {
   int64_t site_updates = 0, ticks = 0, steps_run = 0;
   int keep_fields = 1;
   int use_graph = 0;
+  // scheduling: 0 = every resident job advances every step; 1 = the jobs
+  // of least remaining work (sites x steps), up to fill_sites sites, advance
+  // and the others wait (admission in the same order)
+  int schedule = 1;
+  // 2^23 sites: on a 60-job trace (sides 64-2048) 0.97x the lock-step
+  // throughput at 0.53x its median turnaround; 2^21 gives 0.86x at 0.27x
+  int64_t fill_sites = 1 << 23;
   Clock::time_point t0 = Clock::now();
   std::string err;
 
@@ -81,9 +88,16 @@ int ensure_engine(lb_pool* P, int cls) {
   return LB_OK;
 }
 
-// Admit queued jobs in arrival order while they fit the budget (first fit:
-// a job that does not fit yet does not block later, smaller ones).
+double job_work(const Job& j) { return (double)j.p.nx * (double)j.p.ny * (double)j.steps; }
+
+// Admit queued jobs while they fit the budget (first fit: a job that does
+// not fit yet does not block later, smaller ones), in arrival order or, when
+// scheduling by remaining work, least work first (ties in arrival order).
 int admit(lb_pool* P) {
+  if (P->schedule == 1)
+    std::stable_sort(P->queue.begin(), P->queue.end(), [&](int64_t x, int64_t y) {
+      return job_work(P->jobs[x]) < job_work(P->jobs[y]);
+    });
   for (auto it = P->queue.begin(); it != P->queue.end();) {
     Job& j = P->jobs[*it];
     if (P->resident + j.bytes > P->budget) {
@@ -189,6 +203,14 @@ int lb_pool_set_options(lb_pool* P, int32_t keep_fields, int32_t use_graph) {
   return LB_OK;
 }
 
+int lb_pool_set_schedule(lb_pool* P, int32_t policy, int64_t fill_sites) {
+  if (!P) return LB_E_INVAL;
+  if (policy > 1) return P->fail(LB_E_INVAL, "schedule policy must be 0 or 1");
+  if (policy >= 0) P->schedule = policy;
+  if (fill_sites > 0) P->fill_sites = fill_sites;
+  return LB_OK;
+}
+
 size_t lb_pool_job_bytes(const lb_params* p) {
   return lbe::validate(p, nullptr) == LB_OK ? lbe::member_region_bytes(p) : 0;
 }
@@ -259,21 +281,38 @@ int lb_pool_advance(lb_pool* P, int64_t n) {
     rc = admit(P);
     if (rc != LB_OK) return rc;
     if (left <= 0) break;
-    int64_t m = left;
-    size_t sites = 0;
-    bool any = false;
+    // resident jobs: (class, member, remaining steps, sites)
+    struct Res {
+      int c, i;
+      int64_t rem;
+      size_t sites;
+    };
+    std::vector<Res> rs;
     for (int c = 0; c < 4; ++c) {
       if (!P->eng_ready[c]) continue;
-      for (int i = 0; i < (int)P->eng[c].m.size(); ++i) {
-        m = std::min(m, remaining(P, c, i));
-        sites += (size_t)P->eng[c].m[i].p.nx * P->eng[c].m[i].p.ny;
-        any = true;
-      }
+      for (int i = 0; i < (int)P->eng[c].m.size(); ++i)
+        rs.push_back({c, i, remaining(P, c, i),
+                      (size_t)P->eng[c].m[i].p.nx * P->eng[c].m[i].p.ny});
     }
-    if (!any) break;
+    if (rs.empty()) break;
+    if (P->schedule == 1)  // least remaining work first (stable: ties by class, member)
+      std::stable_sort(rs.begin(), rs.end(), [](const Res& x, const Res& y) {
+        return (double)x.rem * (double)x.sites < (double)y.rem * (double)y.sites;
+      });
+    // the advancing set: everyone (schedule 0), or the least remaining work
+    // until fill_sites sites; it runs until its first job finishes
+    std::vector<int> sel[4];
+    int64_t m = left;
+    size_t sites = 0;
+    for (const Res& r : rs) {
+      if (P->schedule == 1 && sites >= (size_t)P->fill_sites) break;
+      sel[r.c].push_back(r.i);
+      sites += r.sites;
+      m = std::min(m, r.rem);
+    }
     for (int c = 0; c < 4; ++c) {
-      if (!P->eng_ready[c] || P->eng[c].m.empty()) continue;
-      rc = lbe::engine_step(P->eng[c], m);
+      if (sel[c].empty()) continue;
+      rc = lbe::engine_step_subset(P->eng[c], sel[c], m);
       if (rc != LB_OK) return P->fail(rc, P->eng[c].err);
     }
     P->site_updates += (int64_t)sites * m;

@@ -45,14 +45,19 @@ def _alone(sp, steps, seed):
     return lat.fields()["rho"], lat.observables()
 
 
-@pytest.mark.parametrize("budget_frac,use_graph", [(1.0, False), (0.3, False), (0.3, True)])
-def test_pool_results_match_lone_runs(budget_frac, use_graph):
+@pytest.mark.parametrize("budget_frac,use_graph,schedule,fill", [
+    (1.0, False, "lockstep", 0), (0.3, False, "lockstep", 0), (0.3, True, "lockstep", 0),
+    (1.0, False, "srpt", 0), (1.0, False, "srpt", 20000), (0.3, False, "srpt", 9000),
+    (0.3, True, "srpt", 9000)])
+def test_pool_results_match_lone_runs(budget_frac, use_graph, schedule, fill):
+    """Small fill_sites make the least-remaining-work schedule advance a few
+    jobs of a class while the others wait, so every job runs in pieces."""
     lb = _lb()
     jobs = _jobs()
     total = sum(lb.job_bytes(**sp) for sp, _, _ in jobs)
     biggest = max(lb.job_bytes(**sp) for sp, _, _ in jobs)
     budget = max(int(total * budget_frac), biggest)
-    pool = lb.Pool(budget, use_graph=use_graph)
+    pool = lb.Pool(budget, use_graph=use_graph, schedule=schedule, fill_sites=fill)
     ids = []
     for sp, steps, seed in jobs:
         ra, rb = inputs.noise_fields(sp["nx"], sp["ny"], seed, 0.5, 0.5, 0.05)
@@ -72,9 +77,37 @@ def test_pool_results_match_lone_runs(budget_frac, use_graph):
         rho, obs = _alone(sp, steps, seed)
         assert res["obs"]["step"] == steps
         assert np.array_equal(res["rho"], rho), jid
-        assert np.array_equal(res["obs"]["mass"], obs["mass"]), jid
+        for key, val in obs.items():
+            assert np.array_equal(res["obs"][key], val), (jid, key)
         t = res["times"]
         assert t[0] <= t[1] <= t[2]
+    pool.close()
+
+
+def test_srpt_finishes_jobs_in_order_of_work():
+    """With room for one job's sites per step, the least-remaining-work
+    schedule runs the resident jobs one after another, least sites x steps
+    first; each still ends bit for bit as alone."""
+    lb = _lb()
+    jobs = _jobs()
+    pool = lb.Pool(sum(lb.job_bytes(**sp) for sp, _, _ in jobs) * 2, schedule="srpt",
+                   fill_sites=1)
+    ids = []
+    for sp, steps, seed in jobs:
+        ra, rb = inputs.noise_fields(sp["nx"], sp["ny"], seed, 0.5, 0.5, 0.05)
+        ids.append(pool.submit(steps, ra, rb, **sp))
+    pool.advance(sum(steps for _, steps, _ in jobs) + 1)
+    st = pool.stats()
+    assert st["done"] == len(jobs)
+    # one job advances at a time: pool steps are the summed job steps
+    assert st["steps"] == sum(steps for _, steps, _ in jobs)
+    work = [sp["nx"] * sp["ny"] * steps for sp, steps, _ in jobs]
+    done = [pool.result(jid)["times"][2] for jid in ids]
+    order = sorted(range(len(jobs)), key=lambda k: work[k])
+    assert all(done[a] <= done[b] for a, b in zip(order, order[1:])), (work, done)
+    for jid, (sp, steps, seed) in zip(ids, jobs):
+        rho, _ = _alone(sp, steps, seed)
+        assert np.array_equal(pool.result(jid)["rho"], rho), jid
     pool.close()
 
 
