@@ -496,6 +496,9 @@ class Pool(_Handle):
 
     def __init__(self, budget_bytes, stream=None, keep_fields=True, use_graph=False,
                  schedule="srpt", fill_sites=0):
+        policies = {"lockstep": 0, "srpt": 1}
+        if schedule not in policies:
+            raise ValueError(f"schedule must be one of {sorted(policies)}, not {schedule!r}")
         self._lib = load()
         _load_pool_symbols(self._lib)
         self._h = ctypes.c_void_p()
@@ -509,8 +512,7 @@ class Pool(_Handle):
                                              ctypes.byref(self._h)), "lb_pool_create")
         self._check(self._lib.lb_pool_set_options(self._h, int(keep_fields), int(use_graph)),
                     "lb_pool_set_options")
-        policy = {"lockstep": 0, "srpt": 1}[schedule]
-        self._check(self._lib.lb_pool_set_schedule(self._h, policy, int(fill_sites)),
+        self._check(self._lib.lb_pool_set_schedule(self._h, policies[schedule], int(fill_sites)),
                     "lb_pool_set_schedule")
 
     def submit_noise(self, steps, seed, mean_a, mean_b, amp, **spec) -> int:

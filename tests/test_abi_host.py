@@ -84,3 +84,8 @@ def test_library_disc_fields_reject_bad_specs(L):
         phi = kw.pop("phi")
         with pytest.raises(lb.LBError):
             lb.disc_fields(16, 16, 1, phi, **kw)
+
+
+def test_pool_schedule_names_checked_before_any_device_call():
+    with pytest.raises(ValueError):
+        lb.Pool(1 << 20, schedule="fifo")

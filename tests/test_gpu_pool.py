@@ -156,3 +156,18 @@ def test_pool_c5_shapes_against_the_oracle():
             assert np.all(np.abs(res["obs"]["wall_stress"] - ref) <= 1e-8 + 1e-9 * np.abs(ref)), (
                 nx, ny, res["obs"]["wall_stress"], ref)
     pool.close()
+
+
+def test_schedule_setter_arguments():
+    """Policies 0 and 1 are accepted, larger ones refused; negative policy and
+    non-positive fill sizes keep the current settings."""
+    lb = _lb()
+    pool = lb.Pool(1 << 28)
+    f = pool._lib.lb_pool_set_schedule
+    assert f(pool._h, 0, 1 << 20) == 0
+    assert f(pool._h, -1, 0) == 0
+    assert f(pool._h, 1, -5) == 0
+    assert f(pool._h, 2, 1 << 20) == lb.LB_E_INVAL
+    with pytest.raises(ValueError):
+        lb.Pool(1 << 28, schedule="fifo")
+    pool.close()
