@@ -426,16 +426,18 @@ def _job_spec(j, precision):
                 u_wall=j["u_wall"])
 
 
-def replay_trace(trace, budget_bytes, tick_s=0.02, schedule="srpt", fill_sites=0):
+def replay_trace(trace, budget_bytes, tick_s=0.02, schedule="srpt", fill_sites=0, max_hold=0):
     """Replays an arrival trace in real time against a serving pool: each job
     is submitted when its arrival time has passed, the pool is advanced in
     ticks of about tick_s seconds, and a job's time-to-result runs from its
     arrival to the moment its observables and density fields are on the
     host (the pool's clock).  schedule: the pool's ("srpt": least remaining
-    work advances first, up to fill_sites sites, 0 for the pool's default;
-    "lockstep": every resident job every step)."""
+    work advances first, up to fill_sites sites, 0 for the pool's default,
+    a job held back max_hold pool steps first, 0 for no bound; "lockstep":
+    every resident job every step)."""
     from paper_0906_3611_amd import lb
-    pool = lb.Pool(budget_bytes, keep_fields=True, schedule=schedule, fill_sites=fill_sites)
+    pool = lb.Pool(budget_bytes, keep_fields=True, schedule=schedule, fill_sites=fill_sites,
+                   max_hold=max_hold)
     c0 = pool.stats()["clock"]
     t0 = time.perf_counter()
     pending = list(trace)

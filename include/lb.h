@@ -328,11 +328,15 @@ int lb_pool_set_options(lb_pool* pool, int32_t keep_fields, int32_t use_graph);
  * arriving.  A smaller fill_sites trades throughput for turnaround: fewer
  * sites per launch fill the device less (on a 60-job trace with sides 64 to
  * 2048, fill 2^21 gave 0.86x the lock-step throughput at 0.27x its median
- * turnaround, 2^23 0.97x at 0.53x, 2^24 0.99x at 0.83x).  policy 0, lock-step:
- * arrival-order admission, every resident job advances every step.
- * policy < 0 or fill_sites <= 0 keeps that setting; policy > 1 is
- * LB_E_INVAL. */
-int lb_pool_set_schedule(lb_pool* pool, int32_t policy, int64_t fill_sites);
+ * turnaround, 2^23 0.97x at 0.53x, 2^24 0.99x at 0.83x).  max_hold > 0
+ * bounds the wait: a resident job held back for max_hold pool steps in a
+ * row advances in the next chunk, ahead of the order of remaining work
+ * (longest held first, still within fill_sites, at least one job), and a
+ * chunk ends early when a waiting job reaches the bound; 0 (default): no
+ * bound.  policy 0, lock-step: arrival-order admission, every resident job
+ * advances every step.  policy < 0, fill_sites <= 0 or max_hold < 0 keeps
+ * that setting; policy > 1 is LB_E_INVAL. */
+int lb_pool_set_schedule(lb_pool* pool, int32_t policy, int64_t fill_sites, int64_t max_hold);
 /* Device footprint of one job with these parameters (0 if invalid). */
 size_t lb_pool_job_bytes(const lb_params* p);
 /* Queue a job of `steps` steps (p->device_buffer ignored), started from the

@@ -39,6 +39,7 @@ struct Job {
   lb_obs result{};
   std::vector<double> out_a, out_b;  // final densities (done)
   int status = LB_OK;               // failure status
+  int64_t held = 0;                 // pool steps resident without advancing
 };
 
 int engine_class(const lb_params* p) {
@@ -66,6 +67,9 @@ struct lb_pool {
   // 2^23 sites: on a 60-job trace (sides 64-2048) 0.97x the lock-step
   // throughput at 0.53x its median turnaround; 2^21 gives 0.86x at 0.27x
   int64_t fill_sites = 1 << 23;
+  // a resident job held back this many pool steps advances next, ahead of
+  // the order of remaining work (0: no bound)
+  int64_t max_hold = 0;
   Clock::time_point t0 = Clock::now();
   std::string err;
 
@@ -203,11 +207,12 @@ int lb_pool_set_options(lb_pool* P, int32_t keep_fields, int32_t use_graph) {
   return LB_OK;
 }
 
-int lb_pool_set_schedule(lb_pool* P, int32_t policy, int64_t fill_sites) {
+int lb_pool_set_schedule(lb_pool* P, int32_t policy, int64_t fill_sites, int64_t max_hold) {
   if (!P) return LB_E_INVAL;
   if (policy > 1) return P->fail(LB_E_INVAL, "schedule policy must be 0 or 1");
   if (policy >= 0) P->schedule = policy;
   if (fill_sites > 0) P->fill_sites = fill_sites;
+  if (max_hold >= 0) P->max_hold = max_hold;
   return LB_OK;
 }
 
@@ -295,21 +300,36 @@ int lb_pool_advance(lb_pool* P, int64_t n) {
                       (size_t)P->eng[c].m[i].p.nx * P->eng[c].m[i].p.ny});
     }
     if (rs.empty()) break;
-    if (P->schedule == 1)  // least remaining work first (stable: ties by class, member)
-      std::stable_sort(rs.begin(), rs.end(), [](const Res& x, const Res& y) {
+    auto held = [&](const Res& r) -> int64_t& { return P->jobs[P->eng[r.c].m[r.i].tag].held; };
+    if (P->schedule == 1) {
+      // jobs held back to the bound first (longest held first), then least
+      // remaining work (stable: ties by class, member)
+      const int64_t H = P->max_hold;
+      std::stable_sort(rs.begin(), rs.end(), [&](const Res& x, const Res& y) {
+        const bool ox = H > 0 && held(x) >= H, oy = H > 0 && held(y) >= H;
+        if (ox != oy) return ox;
+        if (ox) return held(x) > held(y);
         return (double)x.rem * (double)x.sites < (double)y.rem * (double)y.sites;
       });
-    // the advancing set: everyone (schedule 0), or the least remaining work
-    // until fill_sites sites; it runs until its first job finishes
+    }
+    // the advancing set: everyone (schedule 0), or in that order until
+    // fill_sites sites; it runs until its first job finishes
     std::vector<int> sel[4];
+    std::vector<char> adv(rs.size(), 0);
     int64_t m = left;
     size_t sites = 0;
-    for (const Res& r : rs) {
+    for (size_t k = 0; k < rs.size(); ++k) {
       if (P->schedule == 1 && sites >= (size_t)P->fill_sites) break;
-      sel[r.c].push_back(r.i);
-      sites += r.sites;
-      m = std::min(m, r.rem);
+      sel[rs[k].c].push_back(rs[k].i);
+      adv[k] = 1;
+      sites += rs[k].sites;
+      m = std::min(m, rs[k].rem);
     }
+    // with a hold bound, a chunk also ends when a waiting job reaches it
+    if (P->schedule == 1 && P->max_hold > 0)
+      for (size_t k = 0; k < rs.size(); ++k)
+        if (!adv[k]) m = std::min(m, std::max<int64_t>(1, P->max_hold - held(rs[k])));
+    for (size_t k = 0; k < rs.size(); ++k) held(rs[k]) = adv[k] ? 0 : held(rs[k]) + m;
     for (int c = 0; c < 4; ++c) {
       if (sel[c].empty()) continue;
       rc = lbe::engine_step_subset(P->eng[c], sel[c], m);

@@ -460,7 +460,7 @@ def _load_pool_symbols(L):
         "lb_pool_destroy": ([h], None),
         "lb_pool_last_error": ([h], ctypes.c_char_p),
         "lb_pool_set_options": ([h, i32, i32], ctypes.c_int),
-        "lb_pool_set_schedule": ([h, i32, i64], ctypes.c_int),
+        "lb_pool_set_schedule": ([h, i32, i64, i64], ctypes.c_int),
         "lb_pool_job_bytes": ([P(lb_params)], ctypes.c_size_t),
         "lb_pool_submit_noise": ([h, P(lb_params), ctypes.c_uint64, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_double, i64, P(i64)], ctypes.c_int),
@@ -490,12 +490,13 @@ class Pool(_Handle):
     """Serving pool: jobs admitted under an HBM budget, advanced in launches
     per class, retired with their results copied to the host (see
     include/lb.h).  schedule: "srpt" (least remaining work advances, up to
-    fill_sites sites) or "lockstep" (every resident job, every step)."""
+    fill_sites sites; a job held back max_hold pool steps goes first) or
+    "lockstep" (every resident job, every step)."""
     _destroy = "lb_pool_destroy"
     _last_error = "lb_pool_last_error"
 
     def __init__(self, budget_bytes, stream=None, keep_fields=True, use_graph=False,
-                 schedule="srpt", fill_sites=0):
+                 schedule="srpt", fill_sites=0, max_hold=0):
         policies = {"lockstep": 0, "srpt": 1}
         if schedule not in policies:
             raise ValueError(f"schedule must be one of {sorted(policies)}, not {schedule!r}")
@@ -512,7 +513,8 @@ class Pool(_Handle):
                                              ctypes.byref(self._h)), "lb_pool_create")
         self._check(self._lib.lb_pool_set_options(self._h, int(keep_fields), int(use_graph)),
                     "lb_pool_set_options")
-        self._check(self._lib.lb_pool_set_schedule(self._h, policies[schedule], int(fill_sites)),
+        self._check(self._lib.lb_pool_set_schedule(self._h, policies[schedule], int(fill_sites),
+                                                   int(max_hold)),
                     "lb_pool_set_schedule")
 
     def submit_noise(self, steps, seed, mean_a, mean_b, amp, **spec) -> int:

@@ -45,19 +45,22 @@ def _alone(sp, steps, seed):
     return lat.fields()["rho"], lat.observables()
 
 
-@pytest.mark.parametrize("budget_frac,use_graph,schedule,fill", [
-    (1.0, False, "lockstep", 0), (0.3, False, "lockstep", 0), (0.3, True, "lockstep", 0),
-    (1.0, False, "srpt", 0), (1.0, False, "srpt", 20000), (0.3, False, "srpt", 9000),
-    (0.3, True, "srpt", 9000)])
-def test_pool_results_match_lone_runs(budget_frac, use_graph, schedule, fill):
+@pytest.mark.parametrize("budget_frac,use_graph,schedule,fill,hold", [
+    (1.0, False, "lockstep", 0, 0), (0.3, False, "lockstep", 0, 0),
+    (0.3, True, "lockstep", 0, 0), (1.0, False, "srpt", 0, 0), (1.0, False, "srpt", 20000, 0),
+    (0.3, False, "srpt", 9000, 0), (0.3, True, "srpt", 9000, 0), (1.0, False, "srpt", 9000, 5),
+    (0.3, True, "srpt", 9000, 3)])
+def test_pool_results_match_lone_runs(budget_frac, use_graph, schedule, fill, hold):
     """Small fill_sites make the least-remaining-work schedule advance a few
-    jobs of a class while the others wait, so every job runs in pieces."""
+    jobs of a class while the others wait, so every job runs in pieces; a
+    hold bound cuts the pieces shorter still."""
     lb = _lb()
     jobs = _jobs()
     total = sum(lb.job_bytes(**sp) for sp, _, _ in jobs)
     biggest = max(lb.job_bytes(**sp) for sp, _, _ in jobs)
     budget = max(int(total * budget_frac), biggest)
-    pool = lb.Pool(budget, use_graph=use_graph, schedule=schedule, fill_sites=fill)
+    pool = lb.Pool(budget, use_graph=use_graph, schedule=schedule, fill_sites=fill,
+                   max_hold=hold)
     ids = []
     for sp, steps, seed in jobs:
         ra, rb = inputs.noise_fields(sp["nx"], sp["ny"], seed, 0.5, 0.5, 0.05)
@@ -164,10 +167,40 @@ def test_schedule_setter_arguments():
     lb = _lb()
     pool = lb.Pool(1 << 28)
     f = pool._lib.lb_pool_set_schedule
-    assert f(pool._h, 0, 1 << 20) == 0
-    assert f(pool._h, -1, 0) == 0
-    assert f(pool._h, 1, -5) == 0
-    assert f(pool._h, 2, 1 << 20) == lb.LB_E_INVAL
+    assert f(pool._h, 0, 1 << 20, 0) == 0
+    assert f(pool._h, -1, 0, -1) == 0
+    assert f(pool._h, 1, -5, 100) == 0
+    assert f(pool._h, 2, 1 << 20, 0) == lb.LB_E_INVAL
     with pytest.raises(ValueError):
         lb.Pool(1 << 28, schedule="fifo")
+    pool.close()
+
+
+def test_hold_bound_limits_the_wait():
+    """With room for one job per chunk and a hold bound of H pool steps, no
+    resident job waits more than H steps in a row, so the jobs share the
+    device in turns: the job of most work (200 x 120, 33 steps), last without
+    the bound, now ends before the 96 x 40 job of 60 steps and the 64 x 64
+    job of 40 steps (pool steps 173, 211 and 189 by the selection rule)."""
+    lb = _lb()
+    jobs = _jobs()
+    H = 6
+    pool = lb.Pool(sum(lb.job_bytes(**sp) for sp, _, _ in jobs) * 2, schedule="srpt",
+                   fill_sites=1, max_hold=H)
+    ids = []
+    for sp, steps, seed in jobs:
+        ra, rb = inputs.noise_fields(sp["nx"], sp["ny"], seed, 0.5, 0.5, 0.05)
+        ids.append(pool.submit(steps, ra, rb, **sp))
+    pool.advance(sum(steps for _, steps, _ in jobs) * 2)
+    st = pool.stats()
+    assert st["done"] == len(jobs)
+    assert st["steps"] == sum(steps for _, steps, _ in jobs)  # still one job per chunk
+    done = [pool.result(jid)["times"][2] for jid in ids]
+    assert done[4] < done[2] and done[4] < done[0], done
+    for jid, (sp, steps, seed) in zip(ids, jobs):
+        rho, obs = _alone(sp, steps, seed)
+        res = pool.result(jid)
+        assert np.array_equal(res["rho"], rho), jid
+        for key, val in obs.items():
+            assert np.array_equal(res["obs"][key], val), (jid, key)
     pool.close()
