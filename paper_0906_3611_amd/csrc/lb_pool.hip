@@ -1,8 +1,9 @@
 // Serving pool (C ABI lb_pool_*): simulation jobs are admitted while their
-// device footprint fits an HBM budget, kept resident, advanced together (one
-// launch per step per precision/boundary class, over every resident job),
-// and retired when they reach their step count: observables and density
-// fields are copied to the host and the device memory is released.
+// device footprint fits an HBM budget, kept resident, advanced in launches
+// of one precision/boundary class each (over every resident job of the
+// class, or over those of least remaining work), and retired when they
+// reach their step count: observables and density fields are copied to the
+// host and the device memory is released.
 #include "lb.h"
 #include "lb_engine.h"
 

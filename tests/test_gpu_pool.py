@@ -1,6 +1,6 @@
-"""Serving pool: jobs admitted under an HBM budget and advanced together end
-exactly where the same job run alone ends (bit for bit), whatever else was
-resident; the budget is never exceeded; jobs of the serving trace's extreme
+"""Serving pool: jobs admitted under an HBM budget and advanced in shared
+launches, all together or in turns, end exactly where the same job run alone
+ends (bit for bit), whatever else was resident; the budget is never exceeded; jobs of the serving trace's extreme
 shapes end where the FP64 oracle does, within the storage's tolerance."""
 import numpy as np
 import pytest
