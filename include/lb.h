@@ -19,7 +19,10 @@
  * Conventions for every function below:
  *  - Return value: LB_OK (0) or a negative LB_E_* status.  No function
  *    aborts, exits or throws; the text of the last failure on a handle is
- *    available from lb_last_error().
+ *    available from lb_last_error() (lb_batch_last_error, lb_pool_last_error).
+ *    A create call that fails leaves its reason for the calling thread:
+ *    the same functions return it when given a null handle ("null handle"
+ *    when no create call of this thread has failed since its last success).
  *  - Host arrays are FP64, row-major [ny][nx] with x fastest, whatever the
  *    storage precision, and are only borrowed for the duration of the call.
  *  - Work is enqueued on the HIP stream given at creation (NULL: the null

@@ -69,6 +69,10 @@ struct Engine {
 };
 
 int validate(const lb_params* p, std::string* why);
+// Why the calling thread's last create call failed ("" after a success);
+// read through the last-error functions with a null handle.
+std::string& create_error();
+const char* handle_error(const std::string* handle_err);
 size_t member_region_bytes(const lb_params* p);
 
 // Static engine: n lattices carved from one block (caller's buffer or one

@@ -455,6 +455,16 @@ DeviceGuard::~DeviceGuard() {
   if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
 }
 
+std::string& create_error() {
+  thread_local std::string msg;
+  return msg;
+}
+
+const char* handle_error(const std::string* handle_err) {
+  if (handle_err) return handle_err->c_str();
+  return create_error().empty() ? "null handle" : create_error().c_str();
+}
+
 int validate(const lb_params* p, std::string* why) {
   auto bad = [&](const char* msg) {
     if (why) *why = msg;

@@ -180,10 +180,13 @@ int lb_pool_create(size_t hbm_budget_bytes, void* hip_stream, lb_pool** out) {
   if (!P) return LB_E_NOMEM;
   P->budget = hbm_budget_bytes;
   P->stream = (hipStream_t)hip_stream;
-  if (hipGetDevice(&P->device) != hipSuccess) {
+  const hipError_t e = hipGetDevice(&P->device);
+  if (e != hipSuccess) {
+    lbe::create_error() = std::string("hipGetDevice: ") + hipGetErrorString(e);
     delete P;
     return LB_E_DEVICE;
   }
+  lbe::create_error().clear();
   *out = P;
   return LB_OK;
 }
@@ -195,7 +198,7 @@ void lb_pool_destroy(lb_pool* P) {
   delete P;
 }
 
-const char* lb_pool_last_error(const lb_pool* P) { return P ? P->err.c_str() : "null handle"; }
+const char* lb_pool_last_error(const lb_pool* P) { return lbe::handle_error(P ? &P->err : nullptr); }
 
 int lb_pool_set_options(lb_pool* P, int32_t keep_fields, int32_t use_graph) {
   if (!P) return LB_E_INVAL;

@@ -39,7 +39,7 @@ const char* lb_strerror(int status) {
   }
 }
 
-const char* lb_last_error(const lb_lattice* L) { return L ? L->e.err.c_str() : "null handle"; }
+const char* lb_last_error(const lb_lattice* L) { return lbe::handle_error(L ? &L->e.err : nullptr); }
 
 int lb_workspace_bytes(const lb_params* p, size_t* out) {
   if (!out) return LB_E_INVAL;
@@ -52,13 +52,16 @@ int lb_workspace_bytes(const lb_params* p, size_t* out) {
 int lb_create(const lb_params* p, void* hip_stream, lb_lattice** out) {
   if (!out) return LB_E_INVAL;
   *out = nullptr;
-  const int v = lbe::validate(p, nullptr);
+  std::string why;
+  const int v = lbe::validate(p, &why);
+  lbe::create_error() = why;
   if (v != LB_OK) return v;
   lb_lattice* L = new (std::nothrow) lb_lattice();
   if (!L) return LB_E_NOMEM;
   const int rc = lbe::engine_create_static(L->e, p, 1, p->device_buffer, p->device_bytes,
                                            (hipStream_t)hip_stream);
   if (rc != LB_OK) {
+    lbe::create_error() = L->e.err;
     lbe::engine_destroy(L->e);
     delete L;
     return rc;
@@ -129,7 +132,7 @@ int lb_autotune(lb_lattice* L, int32_t steps, lb_launch_info* out, double* us_pe
 
 /* ------------------------------ batches ------------------------------ */
 
-const char* lb_batch_last_error(const lb_batch* B) { return B ? B->e.err.c_str() : "null handle"; }
+const char* lb_batch_last_error(const lb_batch* B) { return lbe::handle_error(B ? &B->e.err : nullptr); }
 
 int lb_batch_workspace_bytes(const lb_params* p, int32_t n, size_t* out) {
   if (!out) return LB_E_INVAL;
@@ -144,12 +147,14 @@ int lb_batch_create(const lb_params* p, int32_t n, void* device_buffer, size_t d
   if (!out) return LB_E_INVAL;
   *out = nullptr;
   const int v = validate_set(p, n);
+  lbe::create_error() = v != LB_OK ? "invalid parameters or count" : "";
   if (v != LB_OK) return v;
   lb_batch* B = new (std::nothrow) lb_batch();
   if (!B) return LB_E_NOMEM;
   const int rc = lbe::engine_create_static(B->e, p, n, device_buffer, device_bytes,
                                            (hipStream_t)hip_stream);
   if (rc != LB_OK) {
+    lbe::create_error() = B->e.err;
     lbe::engine_destroy(B->e);
     delete B;
     return rc;

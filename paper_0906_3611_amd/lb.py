@@ -214,9 +214,10 @@ class _Handle:
 
     def _check(self, rc, what):
         if rc != LB_OK:
-            msg = ""
-            if getattr(self, "_h", None) and self._h.value:
-                msg = (getattr(self._lib, self._last_error)(self._h) or b"").decode()
+            h = getattr(self, "_h", None)
+            # a null handle reads the reason of this thread's failed create
+            msg = (getattr(self._lib, self._last_error)(h if h and h.value else None)
+                   or b"").decode()
             raise LBError(rc, f"{what}: {self._lib.lb_strerror(rc).decode()}: {msg}")
 
     def close(self):

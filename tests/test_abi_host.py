@@ -48,6 +48,9 @@ def test_invalid_params_rejected(L, bad):
     h = ctypes.c_void_p()
     assert L.lb_create(ctypes.byref(p), None, ctypes.byref(h)) == lb.LB_E_INVAL
     assert not h.value
+    # the failed create leaves its reason for this thread (null handle)
+    why = L.lb_last_error(None).decode()
+    assert why and why != "null handle", why
 
 
 def test_workspace_size_accounts_for_both_buffers(L):
@@ -62,7 +65,13 @@ def test_workspace_size_accounts_for_both_buffers(L):
 def test_status_strings(L):
     for code in (0, -1, -2, -3, -4, -5):
         assert L.lb_strerror(code)
-    assert L.lb_last_error(None) == b"null handle"
+    # a thread with no failed create reads "null handle" for a null handle
+    import threading
+    seen = []
+    t = threading.Thread(target=lambda: seen.append(L.lb_last_error(None)))
+    t.start()
+    t.join()
+    assert seen == [b"null handle"]
     assert L.lb_step(None, 1) == lb.LB_E_INVAL
     assert L.lb_current_step(None) == -1
 
