@@ -41,7 +41,8 @@ class _CParams(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("walls", ctypes.c_int32),
                 ("pad_", ctypes.c_int32), ("tau", ctypes.c_double * 2), ("rho0", ctypes.c_double),
                 ("Ga", ctypes.c_double * 2), ("Gr", ctypes.c_double * 2), ("Gab", ctypes.c_double),
-                ("u_wall", ctypes.c_double), ("g_body", ctypes.c_double)]
+                ("u_wall", ctypes.c_double), ("g_body", ctypes.c_double),
+                ("g_uniform", ctypes.c_double)]
 
 
 @dataclass
@@ -53,7 +54,8 @@ class Params:
     scale.  walls: halfway bounce-back walls below row 0 (x-velocity -u_wall)
     and above row ny-1 (+u_wall); x stays periodic.  g_body: amplitude of the
     shear forcing of Sec. VIII, a force rho_s g_body sin(2 pi y / ny) along x
-    on each species.
+    on each species.  g_uniform: a uniform body force rho_s g_uniform along x
+    on each species (between walls: plane Poiseuille flow).
     """
     nx: int
     ny: int
@@ -65,6 +67,7 @@ class Params:
     walls: bool = False
     u_wall: float = 0.0
     g_body: float = 0.0
+    g_uniform: float = 0.0
 
     def c(self) -> _CParams:
         cp = _CParams()
@@ -76,6 +79,7 @@ class Params:
         cp.Gab = float(self.Gab)
         cp.u_wall = float(self.u_wall)
         cp.g_body = float(self.g_body)
+        cp.g_uniform = float(self.g_uniform)
         return cp
 
 

@@ -98,6 +98,10 @@ typedef struct {
                        each species feels rho_s g(y) along x with
                        g(y) = g_body sin(2 pi y / ny), the force that drives
                        U_x = U0 sin(k y), k = 2 pi / ny (first mode) */
+  double g_uniform; /* uniform body force per unit mass along x: each species
+                       feels rho_s g_uniform (the same kind of volumetric force
+                       as the shear forcing, constant in space; between the
+                       walls it drives plane Poiseuille flow) */
 } lbref_params;
 
 static const double TWO_PI = 6.283185307179586476925286766559;
@@ -175,12 +179,12 @@ void lbref_force(const lbref_params* p, const double* rho, const double* psi, do
           }
         }
         const size_t k = IDX(p, y, x);
-        const double gy = p->g_body * sin(TWO_PI * (double)y / (double)p->ny);
+        const double gy = p->g_body * sin(TWO_PI * (double)y / (double)p->ny) + p->g_uniform;
         for (int a = 0; a < 2; ++a) {
           const double Fa = -p->Ga[s] * ps[k] * att[a];
           const double Fr = -p->Gr[s] * ps[k] * rep1[a] - p->Gr[s] * ps[k] * rep2[a];
           const double FX = -(1.0 / (p->rho0 * p->rho0)) * rs[k] * crs[a];
-          const double Fb = a == 0 ? rs[k] * gy : 0.0; /* body force (Sec. VIII) */
+          const double Fb = a == 0 ? rs[k] * gy : 0.0; /* body forces (Sec. VIII) */
           F[((size_t)s * 2 + a) * n + k] = Fa + Fr + FX + Fb;
         }
       }

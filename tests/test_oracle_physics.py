@@ -8,6 +8,11 @@
   tau = 1 <-> nu = 1/6), with the mixture relaxation time of the Sec. III
   footnote when tau_A != tau_B.
 * Couette flow between moving walls: linear profile and wall stress rho nu du/dy.
+* Plane Poiseuille flow (a uniform body force between walls at rest): the
+  closed-form steady state of BGK with halfway bounce-back, a parabola with
+  a uniform slip g (16 Lambda - 3) / (24 nu), Lambda = (tau - 1/2)^2, so
+  exact at tau = 1/2 + sqrt(3)/4 and second order in 1/H otherwise; each
+  wall takes half the body force.
 * Pure-repulsion bulk densities of a flat interface: Eq. (30) with the
   tau-renormalised rho_g of Eq. (29).
 * Laplace law for pure-repulsion droplets (the test of Sec. V A, Fig. 5):
@@ -273,3 +278,80 @@ def test_interface_indicator_of_a_sine_profile(walls):
     f = oracle.init_equilibrium(p, 0.5 + e * s, 0.5 - e * s)
     t = oracle.totals(p, f)
     assert t["i_ab"] == pytest.approx(e * e * math.sin(k) ** 2 * nx * ny / 2.0, rel=1e-12)
+
+
+# ---------------------------------------------------------------- Poiseuille
+
+def _poiseuille(H, tau, g=1e-6, rho=(0.3, 0.7), nx=5):
+    """Steady plane Poiseuille flow of the non-interacting mixture between
+    walls at rest (rows 0 .. H-1, walls at y = -1/2 and H - 1/2), driven by a
+    uniform body force g per unit mass.  Runs from rest until the slowest
+    mode, exp(-nu (pi / H)^2 t), has decayed by e^-30, then averages the
+    wall momentum over 200 more steps.  Returns (u_x(y), u_y, wall momentum
+    per step and unit length, nu)."""
+    nu = CS2 * (tau - 0.5)
+    steps = int(30.0 / (nu * (math.pi / H) ** 2))
+    p = oracle.Params(nx=nx, ny=H, tau=(tau, tau), rho0=1.0, Ga=(0, 0), Gr=(0, 0), Gab=0.0,
+                      walls=True, u_wall=0.0, g_uniform=g)
+    f = oracle.init_equilibrium(p, np.full((H, nx), rho[0]), np.full((H, nx), rho[1]))
+    f, wm = oracle.run(p, f, steps + 200, avg_from=steps)
+    u = oracle.fields(p, f)["uphys"]
+    assert np.ptp(u[0], axis=1).max() < 1e-15          # no x dependence
+    return u[0][:, 0], u[1], wm / 200 / nx, nu
+
+
+def _parabola(H, g, nu):
+    y = np.arange(H) + 0.5                              # distance from the bottom wall plane
+    return g / (2 * nu) * y * (H - y)
+
+
+def _slip(tau, g, nu):
+    """Uniform slip of the BGK / halfway-bounce-back Poiseuille solution.
+
+    Derivation (steady, linear in g, unidirectional): the populations with
+    c_y = 0 sit at their equilibrium, so with a = f_(1,1) - f_(-1,1) and
+    b = f_(1,-1) - f_(-1,-1) (rho = 1) the momentum is j = 2 tau g + 3 (a + b)
+    and the diagonal pairs obey a(y+1) = (1 - w/2) a + (w/2) b + g/2,
+    b(y-1) = (1 - w/2) b + (w/2) a + g/2 (w = 1/tau).  A quadratic solves
+    these with curvature -g / nu of u = j + g/2; the bounce-back condition
+    a(0) = -b(-1) fixes the constant, which leaves u minus the parabola
+    through the wall planes equal to g ((2 tau - 1)^2 - 3/4) / (2 tau - 1)
+    = g (16 Lambda - 3) / (24 nu), Lambda = (tau - 1/2)^2: zero at
+    Lambda = 3/16, the value for which halfway bounce-back is exact."""
+    lam = (tau - 0.5) ** 2
+    return g * (16 * lam - 3) / (24 * nu)
+
+
+@pytest.mark.parametrize("H", [8, 13])
+def test_poiseuille_exact_at_lambda_3_16(H):
+    tau, g = 0.5 + math.sqrt(3) / 4, 1e-6
+    u, uy, wall, nu = _poiseuille(H, tau, g)
+    par = _parabola(H, g, nu)
+    assert abs(_slip(tau, g, nu)) < 1e-15 * g
+    assert np.abs(u - par).max() < 1e-9 * par.max()
+    assert np.abs(uy).max() < 1e-9 * par.max()        # no cross-channel flow
+    # force balance: each wall takes half of rho g H per unit length
+    assert wall[0] == pytest.approx(0.5 * g * H, rel=1e-9)
+    assert wall[1] == pytest.approx(0.5 * g * H, rel=1e-9)
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0, 1.5])
+def test_poiseuille_slip_closed_form(tau):
+    H, g = 12, 1e-6
+    u, uy, wall, nu = _poiseuille(H, tau, g)
+    dev = u - _parabola(H, g, nu)
+    slip = _slip(tau, g, nu)
+    assert abs(slip) > 1e-3 * u.max()                   # a visible slip at these tau
+    assert np.abs(dev - slip).max() < 1e-9 * u.max()    # the same at every row
+    assert wall.sum() == pytest.approx(g * H, rel=1e-9)
+
+
+def test_poiseuille_error_second_order_in_1_over_H():
+    tau, g = 1.0, 1e-6
+    errs = []
+    for H in (8, 16, 32):
+        u, _, _, nu = _poiseuille(H, tau, g)
+        par = _parabola(H, g, nu)
+        errs.append(np.abs(u - par).max() / par.max())
+    assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.02)
+    assert errs[1] / errs[2] == pytest.approx(4.0, rel=0.02)
