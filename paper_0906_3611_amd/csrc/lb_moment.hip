@@ -67,7 +67,6 @@ __device__ __forceinline__ Coef coef_of(float rref, float r, float vx, float vy)
   const float sq = qxx + qyy;
   const float base = r - 1.5f * sq;  // r - 1.5 A v^2
   Coef c;
-  c.b0 = (4.f / 9.f) * base;
   c.bx = (1.f / 9.f) * (base + 4.5f * qxx);
   c.by = (1.f / 9.f) * (base + 4.5f * qyy);
   c.bd = (1.f / 36.f) * (r + 3.f * sq);  // base + 4.5 A v^2
@@ -75,6 +74,13 @@ __device__ __forceinline__ Coef coef_of(float rref, float r, float vx, float vy)
   c.ax5 = (1.f / 12.f) * ax;             // 3 w_diag; 4 ax5 = 3 w_axis ax exactly
   c.ay5 = (1.f / 12.f) * ay;
   c.r = r;
+  // The nine equilibria of a source sum to b0 + 2 bx + 2 by + 4 bd, which
+  // is r in exact arithmetic (the equilibrium keeps the mass).  With FP32
+  // weights (summing to 1 + 7.45e-9) b0 = (4/9) base would move the mass a
+  // source sends out by that fraction, with the sign of its deviation, and
+  // the total would drift; b0 is therefore what is left of r after the
+  // eight moving equilibria, formed in FP64 (exactly (4/9) base otherwise).
+  c.b0 = (float)((double)r - (2.0 * (double)c.bx + 2.0 * (double)c.by + 4.0 * (double)c.bd));
   return c;
 }
 
@@ -317,8 +323,8 @@ __device__ __forceinline__ void mstep_tile(const LaunchArgs& a, const LatticeDes
         const float psi[2] = {P.pref[0] + c0p.a, P.pref[1] + c0p.b};
         float F[2][2] = {{-psi[0] * Sxa - rho[0] * Xxa, -psi[0] * Sya - rho[0] * Xya},
                          {-psi[1] * Sxb - rho[1] * Xxb, -psi[1] * Syb - rho[1] * Xyb}};
-        if (P.g != 0.f) {
-          const float gy = P.g * sinpi_ct<float>((float)y * P.iny2);
+        if (P.g != 0.f || P.g0 != 0.f) {
+          const float gy = P.g * sinpi_ct<float>((float)y * P.iny2) + P.g0;
           F[0][0] += rho[0] * gy;
           F[1][0] += rho[1] * gy;
         }
@@ -559,8 +565,8 @@ __global__ __launch_bounds__(kWave) void k_mobserve(const LaunchArgs a) {
         const CT psi[2] = {P.pref[0] + c0p.a, P.pref[1] + c0p.b};
         CT F[2][2] = {{-psi[0] * Sxa - rho[0] * Xxa, -psi[0] * Sya - rho[0] * Xya},
                       {-psi[1] * Sxb - rho[1] * Xxb, -psi[1] * Syb - rho[1] * Xyb}};
-        if (P.g != CT(0)) {
-          const CT gy = P.g * sinpi_ct<CT>((CT)y * P.iny2);
+        if (P.g != CT(0) || P.g0 != CT(0)) {
+          const CT gy = P.g * sinpi_ct<CT>((CT)y * P.iny2) + P.g0;
           F[0][0] += rho[0] * gy;
           F[1][0] += rho[1] * gy;
         }

@@ -245,7 +245,8 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
           const CT rho_s = s ? rho1 : rho0;
           const CT psi_s = DEV ? pref + psi_at(0, 0, s) : psi_at(0, 0, s);
           CT Fx = -psi_s * Sx - rho_s * Xx, Fy = -psi_s * Sy - rho_s * Xy;
-          if (P.g != CT(0)) Fx += rho_s * (P.g * sinpi_ct<CT>((CT)y * P.iny2));
+          if (P.g != CT(0) || P.g0 != CT(0))
+            Fx += rho_s * (P.g * sinpi_ct<CT>((CT)y * P.iny2) + P.g0);
           if (!(rho_s > CT(0)) || !(rho_s < CT(1e30))) bad = true;
           // common velocity (Eq. (1) and the definition of u below it)
           const CT inv_den = rcp_ct(rho0 * P.om[0] + rho1 * P.om[1]);
@@ -259,13 +260,32 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
           ST* row = dst + (long long)y * g.row_elems + (s * 9) * kWave;
           CT post[9];
 #pragma unroll
-          for (int i = 0; i < 9; ++i) {
+          for (int i = 1; i < 9; ++i) {
             const CT cu = (CT)cx(i) * vx + (CT)cy(i) * vy;
             const CT poly = cu * (CT(3) + CT(4.5) * cu) - usq;
             const CT feq = DEV ? wq<CT>(i) * (drho + rho_s * poly) : wq<CT>(i) * rho_s * (CT(1) + poly);
             post[i] = f[i] + om * (feq - f[i]);
-            st_at<NT>(row + i * kWave, ob_c, (ST)post[i]);
           }
+          // The collision keeps each species' mass (the equilibrium's zeroth
+          // moment is rho_s).  In FP32 the weights 4/9, 1/9, 1/36 round to
+          // values summing to 1 + 7.45e-9, so an FP32 equilibrium moved a
+          // site's deviation mass by that fraction every step: down in the
+          // phase where the deviation is negative, up in the other, which
+          // left a drift in the total.  The rest population therefore takes
+          // what the site held before the collision minus its eight moving
+          // populations, summed in FP64 (exact for the spans met here): the
+          // site's mass then changes by the final rounding alone.
+          {
+            double before = (double)f[0], moved = 0.0;
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+              before += (double)f[i];
+              moved += (double)post[i];
+            }
+            post[0] = (CT)(before - moved);
+          }
+#pragma unroll
+          for (int i = 0; i < 9; ++i) st_at<NT>(row + i * kWave, ob_c, (ST)post[i]);
           if (WALLS && (y == 0 || y == ny - 1)) {
             // the links leaving towards a wall return with the moving-wall
             // term (halfway bounce-back); their x momentum goes to the wall
