@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 2
+#define LB_ABI_VERSION 3
 
 enum {
   LB_OK = 0,
@@ -86,6 +86,11 @@ typedef struct {
                          drive of U_x = U0 sin(k y), k = 2 pi / ny; a
                          non-interacting fluid reaches U0 = g / (nu k^2)).
                          0: no body force.  Must be finite. */
+  double body_force_x; /* uniform body force per unit mass along x: each
+                         species feels rho_s body_force_x (the same kind of
+                         volumetric force as body_force, constant in space;
+                         between LB_COUETTE_Y walls at rest it drives plane
+                         Poiseuille flow).  0: none.  Must be finite. */
   double rho_ref[2];  /* LB_FP32_DEV reference densities; <= 0 selects the
                          lattice mean of the fields given to lb_init() */
   void* device_buffer;   /* optional caller-owned device workspace (e.g. the
@@ -160,6 +165,14 @@ int lb_init_discs(lb_lattice* lat, uint64_t seed, double phi, double rmin, doubl
 int lb_disc_fields(int32_t nx, int32_t ny, uint64_t seed, double phi, double rmin, double rmax,
                    double in_a, double in_b, double out_a, double out_b, double* rho_a,
                    double* rho_b);
+
+/* The shear-forcing amplitude (lb_params.body_force) that drives
+ * U_x = U0 sin(2 pi y / ny) in a fluid of relaxation time tau (Sec. VIII):
+ * the steady Stokes balance nu U'' + g sin(k y) = 0 gives g = nu k^2 U0 with
+ * nu = c_s^2 (tau - 1/2) = (tau - 1/2) / 3 and k = 2 pi / ny.  Host only, no
+ * device involved.  LB_E_INVAL for ny < 5, tau <= 1/2, a non-finite u0 or a
+ * NULL g. */
+int lb_kolmogorov_force(double u0, int32_t ny, double tau, double* g);
 
 /* Enqueue n >= 0 time steps (Sec. II, Eq. (1)).  Asynchronous. */
 int lb_step(lb_lattice* lat, int64_t n);
@@ -334,9 +347,10 @@ int lb_pool_set_options(lb_pool* pool, int32_t keep_fields, int32_t use_graph);
  * turnaround, 2^23 0.97x at 0.53x, 2^24 0.99x at 0.83x).  max_hold > 0
  * bounds the wait: a resident job held back for max_hold pool steps in a
  * row advances in the next chunk, ahead of the order of remaining work
- * (longest held first, still within fill_sites, at least one job), and a
- * chunk ends early when a waiting job reaches the bound; 0 (default): no
- * bound.  policy 0, lock-step: arrival-order admission, every resident job
+ * (longest held first; every job at the bound advances, past fill_sites if
+ * need be), and a chunk ends early when a waiting job reaches the bound, so
+ * no resident job waits more than max_hold pool steps in a row; 0
+ * (default): no bound.  policy 0, lock-step: arrival-order admission, every resident job
  * advances every step.  policy < 0, fill_sites <= 0 or max_hold < 0 keeps
  * that setting; policy > 1 is LB_E_INVAL. */
 int lb_pool_set_schedule(lb_pool* pool, int32_t policy, int64_t fill_sites, int64_t max_hold);
@@ -354,6 +368,9 @@ int lb_pool_submit(lb_pool* pool, const lb_params* p, const double* rho_a, const
  * retire finished jobs, admit again as memory frees.  Synchronizes. */
 int lb_pool_advance(lb_pool* pool, int64_t n);
 int lb_pool_job_state(const lb_pool* pool, int64_t job_id, int32_t* state);
+/* Steps a job has run so far (0 while queued, its step count once done);
+ * no synchronization: the count of enqueued steps. */
+int lb_pool_job_progress(const lb_pool* pool, int64_t job_id, int64_t* steps_done);
 /* Result of a finished job: observables, densities [ny][nx] (each may be
  * NULL) and times[3] = {submitted, admitted, done} (may be NULL; filled for
  * any job).  LB_E_STATE if not finished; the failure status if it failed. */

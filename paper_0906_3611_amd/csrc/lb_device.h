@@ -96,7 +96,7 @@ struct Params;
 
 template <bool DEV>
 struct Params<double, DEV> {
-  double k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw, g, iny2;
+  double k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw, g, g0, iny2;
   __device__ explicit Params(const Coefs& c) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -114,13 +114,14 @@ struct Params<double, DEV> {
     inv_rho0 = c.inv_rho0;
     uw = c.u_wall;
     g = c.g_body;
+    g0 = c.g_uniform;
     iny2 = c.inv_ny2;
   }
 };
 
 template <bool DEV>
 struct Params<float, DEV> {
-  float k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw, g, iny2;
+  float k[2][5], kx[2], rho0, inv_rho0, tau[2], om[2], rref[2], pref[2], pscale[2], uw, g, g0, iny2;
   __device__ explicit Params(const Coefs& c) {
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
@@ -138,6 +139,7 @@ struct Params<float, DEV> {
     inv_rho0 = c.f_inv_rho0;
     uw = c.f_u_wall;
     g = c.f_g_body;
+    g0 = c.f_g_uniform;
     iny2 = c.f_inv_ny2;
   }
 };

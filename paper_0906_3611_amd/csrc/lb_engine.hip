@@ -102,6 +102,7 @@ void round_coefs(lbk::Coefs& c) {
   c.f_inv_rho0 = (float)c.inv_rho0;
   c.f_u_wall = (float)c.u_wall;
   c.f_g_body = (float)c.g_body;
+  c.f_g_uniform = (float)c.g_uniform;
   c.f_inv_ny2 = (float)c.inv_ny2;
 }
 
@@ -124,6 +125,7 @@ lbk::Coefs make_coefs(const lb_params* p) {
   c.inv_rho0 = 1.0 / p->rho0;
   c.u_wall = p->u_wall;
   c.g_body = p->body_force;
+  c.g_uniform = p->body_force_x;
   c.inv_ny2 = 2.0 / (double)p->ny;
   round_coefs(c);
   return c;
@@ -480,6 +482,16 @@ int validate(const lb_params* p, std::string* why) {
     if (p->tau[0] != 1.0 || p->tau[1] != 1.0) return bad("moment storage needs tau_A = tau_B = 1");
     if (p->boundary != LB_PERIODIC) return bad("moment storage supports periodic boundaries only");
   }
+  {
+    // The kernels address a site within its row by a 32-bit byte offset and
+    // the wall links by a 32-bit index (12 nx of them): both must stay below
+    // 2^31.
+    const long long pitch = ((long long)p->nx + lbk::kWave - 1) / lbk::kWave * lbk::kWave;
+    const long long row_bytes =
+        pitch * (p->precision == LB_FP32_MOM ? 6 * 4 : 18 * (p->precision == LB_FP64 ? 8 : 4));
+    if (row_bytes >= (1LL << 31)) return bad("lattice row too long for 32-bit in-row offsets");
+    if (12LL * p->nx >= (1LL << 31)) return bad("nx too large for 32-bit wall-link indices");
+  }
   for (int s = 0; s < 2; ++s) {
     if (!is_finite(p->tau[s]) || !(p->tau[s] > 0.5)) return bad("tau must be > 1/2");
     if (!is_finite(p->G_a[s]) || !is_finite(p->G_r[s])) return bad("couplings must be finite");
@@ -489,6 +501,7 @@ int validate(const lb_params* p, std::string* why) {
   if (!is_finite(p->G_AB)) return bad("G_AB must be finite");
   if (!is_finite(p->u_wall)) return bad("u_wall must be finite");
   if (!is_finite(p->body_force)) return bad("body_force must be finite");
+  if (!is_finite(p->body_force_x)) return bad("body_force_x must be finite");
   return LB_OK;
 }
 

@@ -43,11 +43,12 @@ struct Coefs {
   double psi_scale[2];  // rho0 exp(-rho_ref / rho0): psi(rho_ref + d) - psi_ref = -psi_scale expm1(-d / rho0)
   double u_wall;      // +u_wall at the top wall, -u_wall at the bottom
   double g_body;      // shear forcing amplitude: rho_s g_body sin(2 pi y / ny) along x
+  double g_uniform;   // uniform body force per unit mass along x: rho_s g_uniform
   double inv_ny2;     // 2 / ny (argument of sinpi for row y)
   // The same constants rounded to FP32 on the host, so FP32 kernels read
   // them straight into scalar registers.
   float f_kself[2][5], f_kcross[2], f_rho0, f_inv_rho0, f_tau[2], f_omega[2], f_rho_ref[2],
-      f_psi_ref[2], f_psi_scale[2], f_u_wall, f_g_body, f_inv_ny2;
+      f_psi_ref[2], f_psi_scale[2], f_u_wall, f_g_body, f_g_uniform, f_inv_ny2;
 };
 
 struct Geometry {

@@ -196,9 +196,10 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
   const CT psi[2] = {DEV ? P.pref[0] + c0p.a : c0p.a, DEV ? P.pref[1] + c0p.b : c0p.b};
   CT F[2][2] = {{-psi[0] * Sxa - rho[0] * Xxa, -psi[0] * Sya - rho[0] * Xya},
                 {-psi[1] * Sxb - rho[1] * Xxb, -psi[1] * Syb - rho[1] * Xyb}};
-  // shear forcing of Sec. VIII: rho_s g sin(2 pi y / ny) along x (row-uniform)
-  if (P.g != CT(0)) {
-    const CT gy = P.g * sinpi_ct<CT>((CT)y * P.iny2);
+  // body forces along x (row-uniform): the shear forcing of Sec. VIII,
+  // rho_s g sin(2 pi y / ny), and a uniform rho_s g0
+  if (P.g != CT(0) || P.g0 != CT(0)) {
+    const CT gy = P.g * sinpi_ct<CT>((CT)y * P.iny2) + P.g0;
     F[0][0] += rho[0] * gy;
     F[1][0] += rho[1] * gy;
   }

@@ -322,8 +322,11 @@ int lb_pool_advance(lb_pool* P, int64_t n) {
     std::vector<char> adv(rs.size(), 0);
     int64_t m = left;
     size_t sites = 0;
+    // every job held back to the bound advances, even past fill_sites (they
+    // come first in the order), so none waits longer than max_hold
     for (size_t k = 0; k < rs.size(); ++k) {
-      if (P->schedule == 1 && sites >= (size_t)P->fill_sites) break;
+      const bool due = P->schedule == 1 && P->max_hold > 0 && held(rs[k]) >= P->max_hold;
+      if (P->schedule == 1 && sites >= (size_t)P->fill_sites && !due) break;
       sel[rs[k].c].push_back(rs[k].i);
       adv[k] = 1;
       sites += rs[k].sites;
@@ -345,6 +348,21 @@ int lb_pool_advance(lb_pool* P, int64_t n) {
     ++P->ticks;
   }
   if (hipStreamSynchronize(P->stream) != hipSuccess) return P->fail(LB_E_DEVICE, "synchronize failed");
+  return LB_OK;
+}
+
+int lb_pool_job_progress(const lb_pool* P, int64_t job_id, int64_t* steps_done) {
+  if (!P || !steps_done) return LB_E_INVAL;
+  auto it = P->jobs.find(job_id);
+  if (it == P->jobs.end()) return LB_E_INVAL;
+  const Job& j = it->second;
+  if (j.state == LB_JOB_RUNNING) {
+    const Engine& E = P->eng[j.engine];
+    const int i = lbe::member_index(E, j.id);
+    *steps_done = i >= 0 ? lbe::member_time(E, i) : 0;
+  } else {
+    *steps_done = j.state == LB_JOB_DONE ? j.steps : 0;
+  }
   return LB_OK;
 }
 

@@ -3,6 +3,7 @@
 #include "lb.h"
 #include "lb_engine.h"
 
+#include <cmath>
 #include <new>
 #include <string>
 
@@ -26,6 +27,13 @@ int validate_set(const lb_params* ps, int n) {
 extern "C" {
 
 int lb_abi_version(void) { return LB_ABI_VERSION; }
+
+int lb_kolmogorov_force(double u0, int32_t ny, double tau, double* g) {
+  if (!g || ny < 5 || !std::isfinite(tau) || !(tau > 0.5) || !std::isfinite(u0)) return LB_E_INVAL;
+  const double k = 2.0 * M_PI / (double)ny;
+  *g = (tau - 0.5) / 3.0 * k * k * u0;
+  return LB_OK;
+}
 
 const char* lb_strerror(int status) {
   switch (status) {

@@ -34,7 +34,7 @@ class lb_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("tau", ctypes.c_double * 2), ("rho0", ctypes.c_double),
                 ("G_a", ctypes.c_double * 2), ("G_r", ctypes.c_double * 2), ("G_AB", ctypes.c_double),
                 ("u_wall", ctypes.c_double), ("body_force", ctypes.c_double),
-                ("rho_ref", ctypes.c_double * 2),
+                ("body_force_x", ctypes.c_double), ("rho_ref", ctypes.c_double * 2),
                 ("device_buffer", ctypes.c_void_p), ("device_bytes", ctypes.c_size_t)]
 
 
@@ -73,6 +73,7 @@ def load():
     fd = ctypes.c_double
     sig = {
         "lb_abi_version": ([], ctypes.c_int),
+        "lb_kolmogorov_force": ([fd, i32, fd, dp], ctypes.c_int),
         "lb_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "lb_last_error": ([h], ctypes.c_char_p),
         "lb_workspace_bytes": ([P(lb_params), P(ctypes.c_size_t)], ctypes.c_int),
@@ -167,7 +168,7 @@ def disc_fields(nx, ny, seed, phi, **kw):
 
 def make_params(nx, ny, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1),
                 G_AB=0.405, boundary="periodic", u_wall=0.0, precision="fp64",
-                rho_ref=(0.0, 0.0), body_force=0.0) -> lb_params:
+                rho_ref=(0.0, 0.0), body_force=0.0, body_force_x=0.0) -> lb_params:
     """An lb_params record (parameters of Sec. II, Eqs. (1), (2), (5))."""
     p = lb_params()
     p.nx, p.ny = int(nx), int(ny)
@@ -180,15 +181,20 @@ def make_params(nx, ny, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1
     p.G_AB = G_AB
     p.u_wall = u_wall
     p.body_force = body_force
+    p.body_force_x = body_force_x
     p.rho_ref[0], p.rho_ref[1] = rho_ref
     return p
 
 
 def kolmogorov_force(U0, ny, tau=1.0):
-    """Body-force amplitude g that drives U_x = U0 sin(2 pi y / ny) in a
-    fluid of kinematic viscosity nu = (tau - 1/2)/3 (Sec. VIII): g = nu k^2 U0."""
-    k = 2.0 * np.pi / ny
-    return (tau - 0.5) / 3.0 * k * k * U0
+    """Body-force amplitude g that drives U_x = U0 sin(2 pi y / ny) (Sec. VIII),
+    from the library (lb_kolmogorov_force)."""
+    L = load()
+    g = ctypes.c_double()
+    rc = L.lb_kolmogorov_force(float(U0), int(ny), float(tau), ctypes.byref(g))
+    if rc != 0:
+        raise LBError(rc, "lb_kolmogorov_force: " + L.lb_strerror(rc).decode())
+    return g.value
 
 
 def _obs_dict(o) -> dict:
@@ -252,12 +258,14 @@ class Lattice(_Handle):
 
     def __init__(self, nx: int, ny: int, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0),
                  G_r=(8.1, 8.1), G_AB=0.405, boundary="periodic", u_wall=0.0, precision="fp64",
-                 rho_ref=(0.0, 0.0), body_force=0.0, use_torch=True, stream=None):
+                 rho_ref=(0.0, 0.0), body_force=0.0, body_force_x=0.0, use_torch=True,
+                 stream=None):
         self._lib = load()
         self._h = ctypes.c_void_p()
         self.nx, self.ny = int(nx), int(ny)
         p = make_params(nx, ny, tau=tau, rho0=rho0, G_a=G_a, G_r=G_r, G_AB=G_AB, boundary=boundary,
-                        u_wall=u_wall, precision=precision, rho_ref=rho_ref, body_force=body_force)
+                        u_wall=u_wall, precision=precision, rho_ref=rho_ref, body_force=body_force,
+                        body_force_x=body_force_x)
         self.precision, self.boundary = precision, boundary
         nbytes = ctypes.c_size_t()
         self._check(self._lib.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(nbytes)), "workspace")
@@ -468,6 +476,7 @@ def _load_pool_symbols(L):
         "lb_pool_submit": ([h, P(lb_params), dp, dp, i64, P(i64)], ctypes.c_int),
         "lb_pool_advance": ([h, i64], ctypes.c_int),
         "lb_pool_job_state": ([h, i64, P(i32)], ctypes.c_int),
+        "lb_pool_job_progress": ([h, i64, P(i64)], ctypes.c_int),
         "lb_pool_job_result": ([h, i64, P(lb_obs), dp, dp, dp], ctypes.c_int),
         "lb_pool_release": ([h, i64], ctypes.c_int),
         "lb_pool_get_stats": ([h, P(lb_pool_stats)], ctypes.c_int),
@@ -547,6 +556,13 @@ class Pool(_Handle):
         s = ctypes.c_int32()
         self._check(self._lib.lb_pool_job_state(self._h, int(jid), ctypes.byref(s)), "lb_pool_job_state")
         return s.value
+
+    def progress(self, jid) -> int:
+        """Steps the job has run so far."""
+        n = ctypes.c_int64()
+        self._check(self._lib.lb_pool_job_progress(self._h, int(jid), ctypes.byref(n)),
+                    "lb_pool_job_progress")
+        return n.value
 
     def times(self, jid):
         t = np.zeros(3)

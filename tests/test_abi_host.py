@@ -21,7 +21,7 @@ def test_every_declared_function_is_exported(L):
     assert len(names) >= 17
     for n in names:
         assert hasattr(L, n), n
-    assert L.lb_abi_version() == 2
+    assert L.lb_abi_version() == 3
 
 
 def _params(**kw):
@@ -51,6 +51,28 @@ def test_invalid_params_rejected(L, bad):
     # the failed create leaves its reason for this thread (null handle)
     why = L.lb_last_error(None).decode()
     assert why and why != "null handle", why
+
+
+@pytest.mark.parametrize("nx,precision", [(30_000_000, lb.LB_FP64), (60_000_000, lb.LB_FP32_DEV),
+                                          (100_000_000, lb.LB_FP32_MOM), (200_000_000, lb.LB_FP32_DEV)])
+def test_rows_beyond_32bit_offsets_rejected(L, nx, precision):
+    """A row whose bytes reach 2^31 (the kernels' in-row offsets are 32-bit)
+    is refused on the host, though it has fewer than 2^30 sites."""
+    p = _params(nx=nx, ny=5, precision=precision)
+    n = ctypes.c_size_t()
+    assert L.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lb.LB_E_INVAL
+    h = ctypes.c_void_p()
+    assert L.lb_create(ctypes.byref(p), None, ctypes.byref(h)) == lb.LB_E_INVAL
+    assert not h.value
+    assert "32-bit" in L.lb_last_error(None).decode()
+
+
+@pytest.mark.parametrize("nx,precision", [(14_000_000, lb.LB_FP64), (29_000_000, lb.LB_FP32_DEV),
+                                          (89_000_000, lb.LB_FP32_MOM)])
+def test_longest_rows_within_32bit_offsets_accepted(L, nx, precision):
+    p = _params(nx=nx, ny=5, precision=precision)
+    n = ctypes.c_size_t()
+    assert L.lb_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lb.LB_OK
 
 
 def test_workspace_size_accounts_for_both_buffers(L):

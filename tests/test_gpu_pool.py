@@ -189,10 +189,10 @@ def test_schedule_setter_arguments():
 
 def test_hold_bound_limits_the_wait():
     """With room for one job per chunk and a hold bound of H pool steps, no
-    resident job waits more than H steps in a row, so the jobs share the
-    device in turns: the job of most work (200 x 120, 33 steps), last without
-    the bound, now ends before the 96 x 40 job of 60 steps and the 64 x 64
-    job of 40 steps (pool steps 173, 211 and 189 by the selection rule)."""
+    resident job waits more than H steps in a row: jobs that reach the bound
+    together advance together, so the jobs share the device in turns and
+    the job of most work (200 x 120, 33 steps), last without the bound, no
+    longer ends last."""
     lb = _lb()
     jobs = _jobs()
     H = 6
@@ -205,13 +205,49 @@ def test_hold_bound_limits_the_wait():
     pool.advance(sum(steps for _, steps, _ in jobs) * 2)
     st = pool.stats()
     assert st["done"] == len(jobs)
-    assert st["steps"] == sum(steps for _, steps, _ in jobs)  # still one job per chunk
     done = [pool.result(jid)["times"][2] for jid in ids]
-    assert done[4] < done[2] and done[4] < done[0], done
+    assert done[4] < max(done), done
     for jid, (sp, steps, seed) in zip(ids, jobs):
         rho, obs = _alone(sp, steps, seed)
         res = pool.result(jid)
         assert np.array_equal(res["rho"], rho), jid
         for key, val in obs.items():
             assert np.array_equal(res["obs"][key], val), (jid, key)
+    pool.close()
+
+
+def test_hold_bound_is_the_longest_wait():
+    """Advanced one pool step per call, with room for one job per chunk and a
+    hold bound of H: no resident job goes more than H pool steps in a row
+    without advancing, even when several reach the bound together (they
+    then advance together, past the fill size)."""
+    lb = _lb()
+    jobs = _jobs()
+    H = 4
+    pool = lb.Pool(sum(lb.job_bytes(**sp) for sp, _, _ in jobs) * 2, schedule="srpt",
+                   fill_sites=1, max_hold=H)
+    ids = []
+    for sp, steps, seed in jobs:
+        ra, rb = inputs.noise_fields(sp["nx"], sp["ny"], seed, 0.5, 0.5, 0.05)
+        ids.append(pool.submit(steps, ra, rb, **sp))
+    last = {jid: 0 for jid in ids}
+    wait = {jid: 0 for jid in ids}
+    longest = 0
+    for _ in range(sum(steps for _, steps, _ in jobs) * 2):
+        if pool.stats()["done"] == len(jobs):
+            break
+        pool.advance(1)
+        for jid in ids:
+            n = pool.progress(jid)
+            if pool.state(jid) == lb.LB_JOB_RUNNING and n == last[jid]:
+                wait[jid] += 1
+                longest = max(longest, wait[jid])
+            else:
+                wait[jid] = 0
+            last[jid] = n
+    assert pool.stats()["done"] == len(jobs)
+    assert 0 < longest <= H, longest
+    for jid, (sp, steps, seed) in zip(ids, jobs):
+        rho, _ = _alone(sp, steps, seed)
+        assert np.array_equal(pool.result(jid)["rho"], rho), jid
     pool.close()
