@@ -77,21 +77,24 @@ def bulk_pressure(rho_a, rho_b, rho0, GA1, GB1, g_ab):
             + CS2 * g_ab * rho_a * rho_b)
 
 
+def psi_sq_integral(r: float, rho0: float) -> float:
+    """I(r) = int_0^r psi(xi)^2 / xi^2 dxi, the self-interaction integral of
+    the bulk free energy (Sec. IV C), by quadrature of its definition."""
+    return integrate.quad(lambda xi: (rho0 * -math.expm1(-xi / rho0)) ** 2 / xi ** 2, 0.0, r,
+                          epsabs=1e-13, epsrel=1e-13)[0]
+
+
 def bulk_free_energy_tau(rho_a, rho_b, tau, rho0, G1, g_ab):
     """tau-renormalised bulk free energy of the symmetric self-interacting
     mixture (Sec. IV C, Eq. (51)) with G^(tau) = G/theta and g^(tau) = g/theta
     (Sec. IV B below Eq. (40)):
       c_s^2 [rho_A log rho_A + rho_B log rho_B + g^(tau) rho_A rho_B
              + G1^(tau)/2 (rho_A I(rho_A) + rho_B I(rho_B))],
-      I(r) = int_0^r psi(xi)^2 / xi^2 dxi."""
+      I = psi_sq_integral."""
     th = theta(tau)
-
-    def I(r):
-        return integrate.quad(lambda xi: (rho0 * -math.expm1(-xi / rho0)) ** 2 / xi ** 2, 0.0, r,
-                              epsabs=1e-13, epsrel=1e-13)[0]
-
     return CS2 * (rho_a * math.log(rho_a) + rho_b * math.log(rho_b) + g_ab / th * rho_a * rho_b
-                  + 0.5 * G1 / th * (rho_a * I(rho_a) + rho_b * I(rho_b)))
+                  + 0.5 * G1 / th * (rho_a * psi_sq_integral(rho_a, rho0)
+                                     + rho_b * psi_sq_integral(rho_b, rho0)))
 
 
 def symmetric_minimum_tau(rho_mean, tau, rho0, G1, g_ab):
@@ -104,3 +107,26 @@ def symmetric_minimum_tau(rho_mean, tau, rho0, G1, g_ab):
                                    options={"xatol": 1e-12})
     phi = res.x
     return (rho_mean + phi) / 2, (rho_mean - phi) / 2
+
+
+def _d1_4th(f):
+    """Fourth-order central difference of a periodic 1-D profile (unit spacing)."""
+    return (8.0 * (np.roll(f, -1) - np.roll(f, 1)) - (np.roll(f, -2) - np.roll(f, 2))) / 12.0
+
+
+def surface_tension_flat(rho_a, rho_b, tau, rho0, GA2, GB2, g_ab, tau_correction=True):
+    """Surface tension from density profiles across flat interfaces (Sec. V,
+    Eqs. (SURFACEFINAL) and (sigmaAB)):
+      c_s^4 int dx [ -G_A2/2 (psi_A')^2 - G_B2/2 (psi_B')^2 - g_AB rho_A' rho_B'
+                     + (tau - 1/2)^2 rho_A rho_B / rho (rho_A'/rho_A - rho_B'/rho_B)^2 ],
+    the last term (the tau-dependent kinetic part K_xx^(tau) of Eq. (PKINTAU))
+    only with tau_correction.  rho_a, rho_b: one periodic row of the profile
+    (unit spacing); derivatives by fourth-order central differences.  The sum
+    runs over the whole row: divide by the number of interfaces in it."""
+    ra, rb = np.asarray(rho_a, float), np.asarray(rho_b, float)
+    da, db = _d1_4th(ra), _d1_4th(rb)
+    pa, pb = _d1_4th(psi(ra, rho0)), _d1_4th(psi(rb, rho0))
+    integrand = -0.5 * GA2 * pa ** 2 - 0.5 * GB2 * pb ** 2 - g_ab * da * db
+    if tau_correction:
+        integrand = integrand + (tau - 0.5) ** 2 * ra * rb / (ra + rb) * (da / ra - db / rb) ** 2
+    return CS2 ** 2 * float(np.sum(integrand))

@@ -355,3 +355,22 @@ def test_poiseuille_error_second_order_in_1_over_H():
         errs.append(np.abs(u - par).max() / par.max())
     assert errs[0] / errs[1] == pytest.approx(4.0, rel=0.02)
     assert errs[1] / errs[2] == pytest.approx(4.0, rel=0.02)
+
+
+def test_self_interacting_bulk_densities():
+    """Fig. 4 couplings (rho0 = 1, <rho> = 1.75, tau = 1, g_AB = 0.5785, first-belt
+    attraction G_1 = G_2 = -0.63 of the inset): a flat slab settles within 2%
+    of the minimum of the tau-renormalised bulk free energy of Sec. IV C
+    (measured 1.0% high, 1.5% low)."""
+    tau, G1, gab, rho_mean, n = 1.0, -0.63, 0.5785, 1.75, 128
+    hi, lo = theory.symmetric_minimum_tau(rho_mean, tau, 1.0, G1, gab)
+    p = oracle.Params(nx=n, ny=5, tau=(tau, tau), rho0=1.0, Ga=(G1, G1), Gr=(0, 0), Gab=gab)
+    x = np.arange(n)
+    inside = (x >= n // 4) & (x < 3 * n // 4)
+    ra = np.repeat(np.where(inside, hi, lo)[None, :], 5, axis=0)
+    rb = np.repeat(np.where(inside, lo, hi)[None, :], 5, axis=0)
+    g, _ = oracle.run(p, oracle.init_equilibrium(p, ra, rb), 20000)
+    r = oracle.density(p, g)
+    assert r[0, 2, n // 2] == pytest.approx(hi, rel=0.02)
+    assert r[1, 2, n // 2] == pytest.approx(lo, rel=0.02)
+    assert r[0, 2, 0] == pytest.approx(lo, rel=0.02)

@@ -1,8 +1,9 @@
 """Pins of the closed forms in oracle/theory.py against numbers the paper prints."""
 import math
 
+import numpy as np
 import pytest
-from scipy import optimize
+from scipy import optimize, special
 
 from conftest import golden_values
 from oracle import theory
@@ -57,3 +58,104 @@ def test_fixing_solution_and_taylor_estimate():
     assert theory.fixing_bulk_densities(3.0, 1.6) == (1.5, 1.5)
     hi, lo = theory.fixing_bulk_densities(3.5, 1.6)
     assert hi - lo == pytest.approx(1.71306, abs=1e-5)
+
+
+@pytest.mark.parametrize("r,rho0", [(0.05, 1.0), (0.7, 1.0), (1.75, 1.0), (3.0, 0.83), (0.4, 0.7)])
+def test_psi_integral_closed_form(r, rho0):
+    """I(r) = int_0^r psi^2 / xi^2 with psi = rho0 (1 - e^(-xi/rho0)) (Eq. (5)):
+    integrating by parts and then Frullani's integral gives, with R = r / rho0,
+    I = rho0 [2 (ln 2 + E1(2R) - E1(R)) - (1 - e^-R)^2 / R]."""
+    R = r / rho0
+    closed = rho0 * (2.0 * (math.log(2.0) + special.exp1(2 * R) - special.exp1(R))
+                     - (-math.expm1(-R)) ** 2 / R)
+    assert theory.psi_sq_integral(r, rho0) == pytest.approx(closed, rel=1e-11)
+
+
+@pytest.mark.parametrize("rho_mean", [3.3, 3.5, 4.0])
+def test_self_interacting_minimum_reduces_to_eq30(rho_mean):
+    """Without self-coupling the tau-renormalised bulk free energy (Sec. IV C)
+    is that of Sec. IV B, whose minimum is the root of Eq. (30) with
+    rho_g^(tau) = theta / g_AB (printed rho_g = 1.6 at tau = 1.116071,
+    g_AB = 0.345)."""
+    tau, gab = G["fig3_tau"], G["fig3_g_AB"]
+    hi, lo = theory.symmetric_minimum_tau(rho_mean, tau, 1.0, 0.0, gab)
+    fhi, flo = theory.fixing_bulk_densities(rho_mean, theory.rho_g_tau(tau, gab))
+    assert hi == pytest.approx(fhi, rel=1e-6) and lo == pytest.approx(flo, rel=1e-6)
+
+
+def _onset_rho_mean(tau, rho0, G1, gab):
+    """<rho> where the curvature of the symmetric bulk free energy at phi = 0
+    vanishes.  With rho_A,B = (<rho> +- phi)/2 and (r I(r))'' = 2 psi psi' / r,
+    f''(0) / c_s^2 = 1/<rho> - g/(2 theta) + G1 psi psi' / (theta <rho>), psi
+    and psi' at <rho>/2; with G1 = 0 the root is 2 rho_g^(tau)."""
+    th = theory.theta(tau)
+
+    def curv(rm):
+        h = rm / 2
+        ps = rho0 * -math.expm1(-h / rho0)
+        dps = math.exp(-h / rho0)
+        return 1.0 / rm - gab / (2 * th) + G1 * ps * dps / (th * rm)
+
+    return optimize.brentq(curv, 1e-3, 50.0)
+
+
+@pytest.mark.parametrize("G1", [0.0, -0.3, G["fig4_G1_inset"]])
+def test_double_well_onset(G1):
+    """The minimiser gives the mixed state below the onset of the double well
+    and two distinct bulks above it (the Fig. 4 couplings)."""
+    tau, rho0, gab = G["fig4_tau"], G["fig4_rho0"], G["fig4_g_AB"]
+    onset = _onset_rho_mean(tau, rho0, G1, gab)
+    if G1 == 0.0:
+        assert onset == pytest.approx(2 * theory.rho_g_tau(tau, gab), rel=1e-12)
+    hi, lo = theory.symmetric_minimum_tau(0.9 * onset, tau, rho0, G1, gab)
+    assert hi - lo < 1e-4 * onset
+    hi, lo = theory.symmetric_minimum_tau(1.1 * onset, tau, rho0, G1, gab)
+    assert hi - lo > 0.1 * onset
+    # stationary: the derivative of the free energy along phi vanishes there
+    fe = lambda phi: theory.bulk_free_energy_tau((1.1 * onset + phi) / 2, (1.1 * onset - phi) / 2,
+                                                 tau, rho0, G1, gab)
+    phi, h = hi - lo, 1e-5
+    assert abs(fe(phi + h) - fe(phi - h)) / (2 * h) < 1e-7
+
+
+def test_flat_surface_tension_integral_of_tanh_profiles():
+    """rho_A = m/2 + (D/2) tanh(x/w), rho_B = m - rho_A (one interface in a
+    long periodic row; the other, far away, is cut off by a second tanh).
+    The bare integrand -g rho_A' rho_B' = g (D/2w)^2 sech^4(x/w) integrates
+    to g D^2 / (3 w); the G_2 terms and the tau term are checked the same way
+    against quadrature of their definitions."""
+    from scipy import integrate
+    n, m, D, g = 2048, 2.7, 1.8, 0.4
+    x = np.arange(n) - n / 4
+
+    def rows(w):
+        ra = m / 2 + D / 2 * (np.tanh(x / w) - np.tanh((x - n / 2) / w) - 1)
+        return ra, m - ra
+
+    errs = []
+    for w in (5.0, 10.0):
+        ra, rb = rows(w)
+        bare = theory.surface_tension_flat(ra, rb, 1.0, 1.0, 0.0, 0.0, g, tau_correction=False)
+        exact = 2 * (1 / 9) * g * D ** 2 / (3 * w)
+        errs.append(abs(bare / exact - 1))
+    assert errs[0] < 1e-3
+    assert 12 < errs[0] / errs[1] < 20          # fourth-order differences
+    w = 10.0
+    ra, rb = rows(w)
+    # the other terms, one interface, against quadrature
+    tau, rho0, GA2, GB2 = 1.3, 0.8, 2.0, -1.5
+
+    def prof(s):
+        a = m / 2 + D / 2 * math.tanh(s / w)
+        da = D / (2 * w) / math.cosh(s / w) ** 2
+        return a, m - a, da, -da
+
+    def integrand(s):
+        a, b, da, db = prof(s)
+        pa, pb = da * math.exp(-a / rho0), db * math.exp(-b / rho0)
+        return (-GA2 / 2 * pa ** 2 - GB2 / 2 * pb ** 2 - g * da * db
+                + (tau - 0.5) ** 2 * a * b / (a + b) * (da / a - db / b) ** 2) / 9
+
+    one = integrate.quad(integrand, -40 * w, 40 * w, epsabs=1e-14, epsrel=1e-12)[0]
+    full = theory.surface_tension_flat(ra, rb, tau, rho0, GA2, GB2, g)
+    assert full == pytest.approx(2 * one, rel=1e-4)
