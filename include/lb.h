@@ -121,6 +121,14 @@ typedef struct {
                             (Sec. VIII, Eq. (67)); grad phi = (1 / c_s^2)
                             sum_{i=1..8} w_i phi(r + c_i) c_i over the force
                             stencil's neighbours (mirrored at walls) */
+  double phi_overlap;    /* sum_r phi(r, t_w) phi(r, t), phi = rho_A - rho_B,
+                            against the reference stored at t_w by
+                            lb_set_overlap_reference (0 without one) */
+  double phi_ref_sq;     /* sum_r phi(r, t_w)^2 (0 without a reference).  The
+                            ageing correlation of Sec. VIII B, Eq. (68), over an
+                            ensemble of lattices is sum phi_overlap over the
+                            realizations / sum phi_ref_sq */
+  int64_t ref_step;      /* t_w, the step of the reference; -1 if none */
 } lb_obs;
 
 typedef struct lb_lattice lb_lattice;
@@ -197,6 +205,13 @@ int lb_set_populations(lb_lattice* lat, const double* f, int64_t step);
 
 /* Restart the wall-stress average at the current step. */
 int lb_reset_averages(lb_lattice* lat);
+
+/* Store the order parameter phi = rho_A - rho_B of the current state (FP64,
+ * on the device, in the lattice's workspace) as the reference of the ageing
+ * overlap (Sec. VIII B, Eq. (68)): from now on lb_observables also reports
+ * sum_r phi_ref phi and sum_r phi_ref^2, reduced in FP64 in a fixed order.
+ * lb_init / lb_set_populations drop the reference.  Synchronizes. */
+int lb_set_overlap_reference(lb_lattice* lat);
 
 /* Wait for all enqueued work; reports LB_E_UNSTABLE if flagged. */
 int lb_sync(lb_lattice* lat);
@@ -290,6 +305,8 @@ int lb_batch_get_populations(lb_batch* b, int32_t i, double* f);
 int lb_batch_sync(lb_batch* b);
 /* Restart the wall-stress averages of every lattice (as lb_reset_averages). */
 int lb_batch_reset_averages(lb_batch* b);
+/* As lb_set_overlap_reference, for every lattice of the batch. */
+int lb_batch_set_overlap_reference(lb_batch* b);
 int lb_batch_get_launch_info(const lb_batch* b, lb_launch_info* out);
 /* As lb_set_launch; seg_h applies to every lattice of the batch (equal
  * tile heights balance the work of uneven lattices). */

@@ -231,13 +231,18 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 // the response mode (Sec. VIII, Eq. (66)) and the interface indicator
 // (Eq. (67)).  f holds the pulled populations (deviations under DEV), atr
 // reads the LDS rho ring at (dy, dx).
+// phi_ref (may be null): the lattice's reference order parameter; with
+// write_ref this site's phi = rho_A - rho_B is stored there first.  Either
+// way the site adds phi_ref phi and phi_ref^2 to the overlap partials (the
+// ageing correlation of Sec. VIII B, Eq. (68)).
 template <typename CT, bool DEV, typename RingR>
 __device__ __forceinline__ void observe_site(double* fields, double* pops, const Geometry& g,
                                              const Params<CT, DEV>& P, int y, int col,
                                              const CT (&rho)[2], const CT (&jx)[2],
                                              const CT (&jy)[2], const CT (&F)[2][2], CT ux, CT uy,
                                              const CT (&f)[2][9], RingR atr,
-                                             double (&acc)[kNRed]) {
+                                             double (&acc)[kNRed], double* phi_ref,
+                                             bool write_ref) {
   const long long site = (long long)y * g.nx + col;
   const long long n = (long long)g.nx * g.ny;
   const double rt = (double)rho[0] + (double)rho[1];
@@ -288,6 +293,13 @@ __device__ __forceinline__ void observe_site(double* fields, double* pops, const
     gby += w3 * py * db;
   }
   acc[8] -= gax * gbx + gay * gby;
+  if (phi_ref) {
+    const double phi = (double)rho[0] - (double)rho[1];
+    if (write_ref) phi_ref[site] = phi;
+    const double w = write_ref ? phi : phi_ref[site];
+    acc[9] += w * phi;
+    acc[10] += w * w;
+  }
 }
 
 }  // namespace

@@ -18,7 +18,8 @@ namespace lbe {
 
 // One lattice of an engine (host view; pointers are device addresses).
 // Its device region holds, in order: two population buffers, two wall-link
-// buffers, its per-tile reduction slots and its flag word.
+// buffers, its per-tile reduction slots, its wall accumulators, its
+// reference order parameter (FP64 per site) and its flag word.
 struct Member {
   lb_params p{};
   lbk::LatticeDesc d{};
@@ -31,6 +32,7 @@ struct Member {
   int64_t e_base = 0;
   int64_t avg_start = 0;       // engine step at which the wall averages restarted
   int64_t tag = 0;             // caller's identifier (pool job id)
+  int64_t ref_time = -1;       // member time of the overlap reference (-1: none)
 };
 
 struct Engine {
@@ -105,6 +107,9 @@ int engine_fields(Engine& E, int i, double* rho_a, double* rho_b, double* u, dou
 int engine_pops(Engine& E, int i, double* f);
 int engine_set_pops(Engine& E, int i, const double* f, int64_t member_t);
 int engine_reset_averages(Engine& E);
+// Store every member's current order parameter rho_A - rho_B as the
+// reference of its overlap sums (synchronizes).
+int engine_set_reference(Engine& E);
 int engine_sync(Engine& E);
 int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32_t use_graph);
 int engine_regrid(Engine& E, int seg_h);

@@ -188,6 +188,8 @@ Member make_member(const lb_params* p, char* region, bool owns, int64_t tag) {
   q += align_up(red_slots(p) * lbk::kNRed * sizeof(double));
   mm.d.wave_wall = (double*)q;
   q += align_up(wall_slots(p) * 2 * sizeof(double));
+  mm.d.phi_ref = (double*)q;
+  q += align_up((size_t)p->nx * (size_t)p->ny * sizeof(double));
   mm.d.flag = (int*)q;
   mm.d.phase = 0;
   return mm;
@@ -345,6 +347,8 @@ void begin_member(Engine& E, int i, int64_t member_t) {
   mm.e_base = E.step;
   mm.avg_start = E.step;
   mm.initialized = true;
+  mm.d.has_ref = 0;  // a new state has no overlap reference yet
+  mm.ref_time = -1;
 }
 
 int zero_member_slots(Engine& E, int i) {
@@ -443,6 +447,9 @@ void fill_obs(const Engine& E, int i, const double* h, int flag, lb_obs* out) {
   }
   out->u_mode = h[7] * 2.0 / ((double)mm.d.g.nx * (double)mm.d.g.ny);
   out->i_ab = h[8];
+  out->phi_overlap = h[9];
+  out->phi_ref_sq = h[10];
+  out->ref_step = mm.ref_time;
   out->flags = flag;
 }
 
@@ -510,7 +517,8 @@ size_t member_region_bytes(const lb_params* p) {
   const size_t pop = align_up((size_t)g.row_elems * (size_t)g.ny * elem_size(p));
   const size_t wall = align_up(12ull * (size_t)p->nx * elem_size(p));
   return 2 * pop + 2 * wall + align_up(red_slots(p) * lbk::kNRed * sizeof(double)) +
-         align_up(wall_slots(p) * 2 * sizeof(double)) + kAlign;
+         align_up(wall_slots(p) * 2 * sizeof(double)) +
+         align_up((size_t)p->nx * (size_t)p->ny * sizeof(double)) + kAlign;
 }
 
 size_t engine_static_bytes(const lb_params* ps, int n) {
@@ -892,6 +900,24 @@ int engine_reset_averages(Engine& E) {
     mm.avg_start = E.step;
   }
   return LB_OK;
+}
+
+int engine_set_reference(Engine& E) {
+  for (auto& mm : E.m)
+    if (!mm.initialized) return E.fail(LB_E_STATE, "reference before every lattice is initialized");
+  if (E.m.empty()) return LB_OK;
+  DeviceGuard dg(E.device);
+  lbk::LaunchArgs a = launch_args(E, (int)(E.step & 1));
+  a.write_ref = 1;
+  HIPCK(E, observe_launch(E, a, E.stream));
+  for (int i = 0; i < (int)E.m.size(); ++i) {
+    E.m[i].d.has_ref = 1;
+    E.m[i].ref_time = member_time(E, i);
+  }
+  drop_graphs(E);
+  const int rc = upload_descs(E);  // synchronizes
+  if (rc != LB_OK) return rc;
+  return read_flags(E, nullptr);
 }
 
 int engine_sync(Engine& E) {

@@ -26,8 +26,11 @@ __host__ __device__ inline long long pop_index(long long row_elems, int s, int i
   return (long long)y * row_elems + (long long)(x >> 6) * (18 * 64) + (s * 9 + i) * 64 + (x & 63);
 }
 
-// Number of FP64 values each wave writes in observe mode.
-constexpr int kNRed = 10;  // massA, massB, momx, momy, momphys_x, momphys_y, pxy, u_mode, i_ab, spare
+// Number of FP64 values each wave writes in observe mode: massA, massB,
+// momx, momy, momphys_x, momphys_y, pxy, u_mode, i_ab, and the two sums of
+// the overlap against the reference order parameter, sum phi_ref phi and
+// sum phi_ref^2.
+constexpr int kNRed = 11;
 
 // Physical constants of one lattice, in FP64 (converted per kernel).
 struct Coefs {
@@ -68,6 +71,8 @@ struct LatticeDesc {
   int* flag;      // bit 0 set when a density is non-finite or <= 0
   double* wave_red;   // observe: kNRed partials per (row, strip) of this lattice
   double* wave_wall;  // step: wall-momentum accumulators (bottom, top) per strip
+  double* phi_ref;    // reference order parameter rho_A - rho_B per site [ny][nx] (FP64)
+  int has_ref;        // phi_ref holds a reference: observe adds the overlap sums
   int tile_base;  // first tile of this lattice in its launch's tile list
   int phase;      // with launch step parity p the lattice reads buf[p ^ phase]
   int local[2];   // moment storage: buf[k] holds site-local equilibria (t = 0 form)
@@ -84,6 +89,7 @@ struct LaunchArgs {
   double* fields;            // observe, single lattice: [6][ny][nx] or null
   double* pops;              // observe, single lattice: [2][9][ny][nx] or null
   int accumulate_wall;       // step: add wall momentum to the lattices' wave_wall
+  int write_ref;             // observe: store each lattice's phi as its reference first
 };
 
 // Code variants of the step kernel (tuning choices, same arithmetic).

@@ -146,6 +146,8 @@ struct Out {
   ST* wall_out;   // wall links for t + 1
   double* fields;  // observe outputs (single-lattice launches)
   double* pops;
+  double* phi_ref;  // observe: the reference order parameter, or null
+  bool write_ref;   // observe: store phi as the reference first
 };
 
 template <typename CT, bool DEV, bool WALLS, int MODE, typename ST, bool NT>
@@ -216,7 +218,8 @@ __device__ __forceinline__ void collide_row(const Out<ST>& a, const Params<CT, D
   const CT uy = (jy[0] * P.om[0] + jy[1] * P.om[1]) * inv_den;
 
   if (MODE == kObserve) {
-    observe_site<CT, DEV>(a.fields, a.pops, g, P, y, col, rho, jx, jy, F, ux, uy, f, atr, acc);
+    observe_site<CT, DEV>(a.fields, a.pops, g, P, y, col, rho, jx, jy, F, ux, uy, f, atr, acc,
+                          a.phi_ref, a.write_ref);
     return;
   }
 
@@ -315,7 +318,9 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
   const Params<CT, DEV> P(D->c);
   const ST* __restrict__ src = (const ST*)D->buf[sel];
   const ST* __restrict__ wall_in = (const ST*)D->wall[sel];
-  const Out<ST> out{g, (ST*)D->buf[sel ^ 1], (ST*)D->wall[sel ^ 1], a.fields, a.pops};
+  const bool ref_on = MODE == kObserve && (a.write_ref || D->has_ref);
+  const Out<ST> out{g, (ST*)D->buf[sel ^ 1], (ST*)D->wall[sel ^ 1], a.fields, a.pops,
+                    ref_on ? D->phi_ref : nullptr, a.write_ref != 0};
 
   CT fr[NSET][2][9];  // pulled rows, set k % NSET for march row k
   ST ri[NSET][2];     // this lane's ring items of those rows

@@ -578,7 +578,8 @@ __global__ __launch_bounds__(kWave) void k_mobserve(const LaunchArgs a) {
         const CT ux = (jx[0] * P.om[0] + jx[1] * P.om[1]) * inv_den;
         const CT uy = (jy[0] * P.om[0] + jy[1] * P.om[1]) * inv_den;
         observe_site<CT, true>(a.fields, a.pops, g, P, y, col, rho, jx, jy, F, ux, uy, fo[jc], atr,
-                               acc);
+                               acc, (a.write_ref || D->has_ref) ? D->phi_ref : nullptr,
+                               a.write_ref != 0);
       }
       if (k >= 4) {
         const long long rs = ((long long)lattice_row(k - 2) * g.nstrips + strip) * kNRed;

@@ -113,6 +113,10 @@ int lb_set_populations(lb_lattice* L, const double* f, int64_t step) {
 
 int lb_reset_averages(lb_lattice* L) { return L ? lbe::engine_reset_averages(L->e) : LB_E_INVAL; }
 
+int lb_set_overlap_reference(lb_lattice* L) {
+  return L ? lbe::engine_set_reference(L->e) : LB_E_INVAL;
+}
+
 int lb_sync(lb_lattice* L) { return L ? lbe::engine_sync(L->e) : LB_E_INVAL; }
 
 int64_t lb_current_step(const lb_lattice* L) { return L ? lbe::member_time(L->e, 0) : -1; }
@@ -222,6 +226,10 @@ int lb_batch_set_launch(lb_batch* B, int32_t seg_h, int32_t prefetch, int32_t st
 
 int lb_batch_reset_averages(lb_batch* B) {
   return B ? lbe::engine_reset_averages(B->e) : LB_E_INVAL;
+}
+
+int lb_batch_set_overlap_reference(lb_batch* B) {
+  return B ? lbe::engine_set_reference(B->e) : LB_E_INVAL;
 }
 
 int lb_batch_autotune(lb_batch* B, int32_t steps, lb_launch_info* out, double* us_per_step) {

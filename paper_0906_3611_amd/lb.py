@@ -43,7 +43,8 @@ class lb_obs(ctypes.Structure):
                 ("mom_phys", ctypes.c_double * 2), ("pxy_kin", ctypes.c_double),
                 ("wall_stress", ctypes.c_double * 2), ("avg_count", ctypes.c_int64),
                 ("flags", ctypes.c_int32), ("pad_", ctypes.c_int32), ("u_mode", ctypes.c_double),
-                ("i_ab", ctypes.c_double)]
+                ("i_ab", ctypes.c_double), ("phi_overlap", ctypes.c_double),
+                ("phi_ref_sq", ctypes.c_double), ("ref_step", ctypes.c_int64)]
 
 
 class lb_launch_info(ctypes.Structure):
@@ -89,6 +90,8 @@ def load():
         "lb_get_populations": ([h, dp], ctypes.c_int),
         "lb_set_populations": ([h, dp, i64], ctypes.c_int),
         "lb_reset_averages": ([h], ctypes.c_int),
+        "lb_set_overlap_reference": ([h], ctypes.c_int),
+        "lb_batch_set_overlap_reference": ([h], ctypes.c_int),
         "lb_sync": ([h], ctypes.c_int),
         "lb_current_step": ([h], i64),
         "lb_get_launch_info": ([h, P(lb_launch_info)], ctypes.c_int),
@@ -201,7 +204,8 @@ def _obs_dict(o) -> dict:
     return {"step": o.step, "mass": np.array(o.mass[:]), "mom": np.array(o.mom[:]),
             "mom_phys": np.array(o.mom_phys[:]), "pxy_kin": o.pxy_kin,
             "wall_stress": np.array(o.wall_stress[:]), "avg_count": o.avg_count,
-            "flags": o.flags, "u_mode": o.u_mode, "i_ab": o.i_ab}
+            "flags": o.flags, "u_mode": o.u_mode, "i_ab": o.i_ab, "phi_overlap": o.phi_overlap,
+            "phi_ref_sq": o.phi_ref_sq, "ref_step": o.ref_step}
 
 
 def _info_dict(li) -> dict:
@@ -330,6 +334,10 @@ class Lattice(_Handle):
     def reset_averages(self):
         self._check(self._lib.lb_reset_averages(self._h), "lb_reset_averages")
 
+    def set_overlap_reference(self):
+        """Store phi = rho_A - rho_B now as the reference of the overlap sums."""
+        self._check(self._lib.lb_set_overlap_reference(self._h), "lb_set_overlap_reference")
+
     def sync(self):
         self._check(self._lib.lb_sync(self._h), "lb_sync")
 
@@ -428,6 +436,11 @@ class Batch(_Handle):
 
     def reset_averages(self):
         self._check(self._lib.lb_batch_reset_averages(self._h), "lb_batch_reset_averages")
+
+    def set_overlap_reference(self):
+        """As Lattice.set_overlap_reference, for every lattice of the batch."""
+        self._check(self._lib.lb_batch_set_overlap_reference(self._h),
+                    "lb_batch_set_overlap_reference")
 
     def launch_info(self) -> dict:
         li = lb_launch_info()
