@@ -193,6 +193,17 @@ int lb_observables(lb_lattice* lat, lb_obs* out);
  * [2][ny][nx] = (sum_s j_s + F/2) / (rho_A + rho_B).  Synchronizes. */
 int lb_get_fields(lb_lattice* lat, double* rho_a, double* rho_b, double* u, double* u_phys);
 
+/* lb_get_fields without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, outputs and errors as lb_get_fields,
+ * except: the fields are staged in a static device array of 48 MiB per GPU
+ * (held until the process ends), so the lattice may have at most 2^20 sites
+ * (LB_E_INVAL otherwise, with the reason in lb_last_error); calls that
+ * overlap in time on one GPU share that array and race, so the caller must
+ * serialize them.  Synchronizes. */
+int lb_get_fields_noalloc(lb_lattice* lat, double* rho_a, double* rho_b, double* u,
+                          double* u_phys);
+
 /* Pre-collision populations f_is(r, t) of the current state into host
  * f[2][9][ny][nx] (FP64, D2Q9 order rest, +x, +y, -x, -y, (1,1), (-1,1),
  * (-1,-1), (1,-1)).  Synchronizes. */

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liblbsoft.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("lb_kernels.hip", "lb_engine.hip", "lb_runtime.hip", "lb_pool.hip", "lb_init_spec.hip", "lb_moment.hip", "lb_split.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("lb_kernels.hip", "lb_engine.hip", "lb_runtime.hip", "lb_pool.hip", "lb_init_spec.hip", "lb_moment.hip", "lb_split.hip", "lb_noalloc.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -104,6 +104,10 @@ int engine_step_subset(Engine& E, const std::vector<int>& sel, int64_t n);
 int engine_observables(Engine& E, lb_obs* out /*[members]*/);
 int engine_member_observables(Engine& E, int i, lb_obs* out);
 int engine_fields(Engine& E, int i, double* rho_a, double* rho_b, double* u, double* u_phys);
+// The same through a caller's device staging buffer of 6 nx ny doubles
+// (allocates nothing; checks member i's flag only).
+int engine_fields_staged(Engine& E, int i, double* staging, double* rho_a, double* rho_b,
+                         double* u, double* u_phys);
 int engine_pops(Engine& E, int i, double* f);
 int engine_set_pops(Engine& E, int i, const double* f, int64_t member_t);
 int engine_reset_averages(Engine& E);

@@ -828,6 +828,28 @@ int engine_member_observables(Engine& E, int i, lb_obs* out) {
   return LB_OK;
 }
 
+int engine_fields_staged(Engine& E, int i, double* staging, double* rho_a, double* rho_b,
+                         double* u, double* u_phys) {
+  if (i < 0 || i >= (int)E.m.size()) return E.fail(LB_E_INVAL, "lattice index out of range");
+  if (!E.m[i].initialized) return E.fail(LB_E_STATE, "fields before lb_init");
+  DeviceGuard dg(E.device);
+  const size_t n = (size_t)E.m[i].d.g.nx * E.m[i].d.g.ny, nb = n * sizeof(double);
+  double* d = staging;
+  lbk::LaunchArgs a = member_args(E, i);
+  a.fields = d;  // every site of all six fields is written
+  HIPCK(E, observe_launch(E, a, E.stream));
+  if (rho_a) HIPCK(E, hipMemcpyAsync(rho_a, d, nb, hipMemcpyDeviceToHost, E.stream));
+  if (rho_b) HIPCK(E, hipMemcpyAsync(rho_b, d + n, nb, hipMemcpyDeviceToHost, E.stream));
+  if (u) HIPCK(E, hipMemcpyAsync(u, d + 2 * n, 2 * nb, hipMemcpyDeviceToHost, E.stream));
+  if (u_phys) HIPCK(E, hipMemcpyAsync(u_phys, d + 4 * n, 2 * nb, hipMemcpyDeviceToHost, E.stream));
+  // the member's own flag word, read without host containers
+  int flag = 0;
+  HIPCK(E, hipMemcpyAsync(&flag, E.m[i].d.flag, sizeof(int), hipMemcpyDeviceToHost, E.stream));
+  HIPCK(E, hipStreamSynchronize(E.stream));
+  if (flag & 1) return E.fail(LB_E_UNSTABLE, "non-finite or non-positive density on the device");
+  return LB_OK;
+}
+
 int engine_fields(Engine& E, int i, double* rho_a, double* rho_b, double* u, double* u_phys) {
   if (i < 0 || i >= (int)E.m.size()) return E.fail(LB_E_INVAL, "lattice index out of range");
   if (!E.m[i].initialized) return E.fail(LB_E_STATE, "fields before lb_init");
@@ -835,14 +857,8 @@ int engine_fields(Engine& E, int i, double* rho_a, double* rho_b, double* u, dou
   const size_t n = (size_t)E.m[i].d.g.nx * E.m[i].d.g.ny, nb = n * sizeof(double);
   DevTmp t;
   HIPCK(E, hipMalloc(&t.p, 6 * nb));
-  double* d = (double*)t.p;
-  lbk::LaunchArgs a = member_args(E, i);
-  a.fields = d;
-  HIPCK(E, observe_launch(E, a, E.stream));
-  if (rho_a) HIPCK(E, hipMemcpyAsync(rho_a, d, nb, hipMemcpyDeviceToHost, E.stream));
-  if (rho_b) HIPCK(E, hipMemcpyAsync(rho_b, d + n, nb, hipMemcpyDeviceToHost, E.stream));
-  if (u) HIPCK(E, hipMemcpyAsync(u, d + 2 * n, 2 * nb, hipMemcpyDeviceToHost, E.stream));
-  if (u_phys) HIPCK(E, hipMemcpyAsync(u_phys, d + 4 * n, 2 * nb, hipMemcpyDeviceToHost, E.stream));
+  const int rc = engine_fields_staged(E, i, (double*)t.p, rho_a, rho_b, u, u_phys);
+  if (rc != LB_OK) return rc;
   return read_flags(E, nullptr);
 }
 

@@ -87,6 +87,7 @@ def load():
         "lb_step": ([h, i64], ctypes.c_int),
         "lb_observables": ([h, P(lb_obs)], ctypes.c_int),
         "lb_get_fields": ([h, dp, dp, dp, dp], ctypes.c_int),
+        "lb_get_fields_noalloc": ([h, dp, dp, dp, dp], ctypes.c_int),
         "lb_get_populations": ([h, dp], ctypes.c_int),
         "lb_set_populations": ([h, dp, i64], ctypes.c_int),
         "lb_reset_averages": ([h], ctypes.c_int),
