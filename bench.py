@@ -1,17 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the two-species Shan-Chen D2Q9 step on one MI355X.
 
-Workload (default): a 1024 x 1024 periodic lattice with the rho0 = 0.83
-standard couplings (G^a = -9.0, G^r = 8.1 for both species, G_AB = 0.405,
-tau = 1), started from a seeded disc emulsion (volume fraction 0.7, radii
-6-12, rho_A = 1.2 / rho_B = 0.05 inside, swapped outside), advanced with
-FP32-deviation population storage.  One "step" is one full time step of the
-model (forces, collision and streaming of both species), i.e. one launch of
-the step kernel.  The same run in FP64 storage is reported beside it.
+Workload of the headline (default): the planar Couette channel, 4096 x 1024
+sites, halfway bounce-back walls moving at -/+0.005 on y, periodic in x,
+the rho0 = 0.83 standard couplings (G^a = -9.0, G^r = 8.1 for both species,
+G_AB = 0.405, tau = 1), started from the seeded mixture 0.5 +- 0.01 per
+species (seed 3), advanced with FP32-deviation population storage: 604 MB
+of populations, larger than the 256 MB Infinity Cache, so every step streams
+from HBM.  One "step" is one full time step of the model (forces, collision
+and streaming of both species), i.e. one launch of the step kernel.
 
 Printed: one JSON line with two-species MLUPS (10^6 site updates per second,
-each advancing both species), the step kernel's HBM roofline figures, and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+each advancing both species), the step kernel's HBM roofline figures beside
+the ceiling a hand-written streaming copy reaches on this GPU, the FP64 CPU
+oracle timed on a bounded sample of the same workload, and the other
+workloads (the 1024^2 emulsion, FP64 and moment storages, the precision
+study against the oracle, batched ensembles, the serving trace) as extra keys.
 """
 from __future__ import annotations
 
@@ -33,6 +37,7 @@ PAPER_MLUPS = 1024 * 1024 * 1e6 / 86400 / 1e6  # 1024^2, 1e6 steps in about one 
 BYTES_PER_SITE = {"fp32dev": 144, "fp64": 288, "fp32mom": 48}
 # step kernel of each storage on a periodic lattice
 STEP_KERNEL = {"fp32dev": "k_split", "fp64": "k_march (step)", "fp32mom": "k_mstep"}
+HEADLINE_U = 0.005  # wall speed of the headline channel (the middle of 0.001, 0.005, 0.02)
 PARAMS = dict(tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1, 8.1), G_AB=0.405)
 # sources of each storage's periodic step kernel (a measurement is valid
 # while they are unchanged)
@@ -84,10 +89,16 @@ def time_steps(lat, steps: int, warmup: int):
     return e0.elapsed_time(e1)  # ms
 
 
-def run_gpu(nx, ny, precision, steps, warmup, rho_a, rho_b, boundary="periodic", u_wall=0.0):
+def run_gpu(nx, ny, precision, steps, warmup, rho_a, rho_b, boundary="periodic", u_wall=0.0,
+            tune_steps=0):
+    """One lattice: initialize, optionally autotune its launch shape on its
+    own state (lb_autotune restores the state, so the evolution is
+    unchanged), warm up, time `steps` steps."""
     from paper_0906_3611_amd import lb
     lat = lb.Lattice(nx, ny, precision=precision, boundary=boundary, u_wall=u_wall, **PARAMS)
     lat.init(rho_a, rho_b)
+    mass0 = lat.observables()["mass"]
+    tuned = lat.autotune(steps=tune_steps) if tune_steps else None
     ms = time_steps(lat, steps, warmup)
     obs = lat.observables()  # raises on instability
     info = lat.launch_info()
@@ -97,8 +108,11 @@ def run_gpu(nx, ny, precision, steps, warmup, rho_a, rho_b, boundary="periodic",
     mlups = sites * steps / (ms * 1e-3) / 1e6
     ms_step = ms / steps
     gbs = BYTES_PER_SITE[precision] * sites / (ms_step * 1e-3) / 1e9
-    return {"mlups": mlups, "ms_per_step": ms_step, "achieved_gbs": gbs, "obs": obs, "info": info,
-            "rho": rho}
+    out = {"mlups": mlups, "ms_per_step": ms_step, "achieved_gbs": gbs, "obs": obs, "info": info,
+           "rho": rho, "mass_rel_drift": [abs(obs["mass"][k] / mass0[k] - 1.0) for k in (0, 1)]}
+    if tuned:
+        out["autotune"] = tuned
+    return out
 
 
 def _cpu_model() -> str:
@@ -122,20 +136,20 @@ def _oracle_rate(oracle, p, f, budget_s, max_steps):
     return p.nx * p.ny * n / dt / 1e6, n, dt
 
 
-def cpu_baseline(nx, ny, rho_a, rho_b, budget_s=10.0):
+def cpu_baseline(nx, ny, rho_a, rho_b, walls=False, u_wall=0.0, label="", budget_s=15.0):
     """The FP64 oracle on the host cores (all OpenMP threads, then one), on a
     bounded number of steps of the same workload."""
     import oracle
     p = oracle.Params(nx=nx, ny=ny, tau=PARAMS["tau"], rho0=PARAMS["rho0"], Ga=PARAMS["G_a"],
-                      Gr=PARAMS["G_r"], Gab=PARAMS["G_AB"])
+                      Gr=PARAMS["G_r"], Gab=PARAMS["G_AB"], walls=walls, u_wall=u_wall)
     f = oracle.init_equilibrium(p, rho_a, rho_b)
     cores = oracle.max_threads()
     v, n, dt = _oracle_rate(oracle, p, f, budget_s, 60)
     oracle.set_threads(1)
-    v1, n1, dt1 = _oracle_rate(oracle, p, f, budget_s / 2, 10)
+    v1, n1, dt1 = _oracle_rate(oracle, p, f, budget_s / 3, 10)
     oracle.set_threads(cores)
     return {"value": v, "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{nx}x{ny} disc emulsion, FP64, {n} steps after 1 untimed, {dt:.1f} s",
+            "sample": f"{label}, FP64, {n} steps after 1 untimed, {dt:.1f} s",
             "value_1_thread": v1, "sample_1_thread": f"{n1} steps, {dt1:.1f} s",
             "cpu": _cpu_model(), "nproc": os.cpu_count()}
 
@@ -194,6 +208,7 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
     for U in speeds:
         lat = lb.Lattice(nx, ny, precision="fp32dev", boundary="couette", u_wall=U, **PARAMS)
         lat.init(ra, rb)
+        m0 = lat.observables()["mass"]
         h = steps // 2
         ms = _timed(lat.stream, lambda: lat.step(h))
         lat.reset_averages()
@@ -202,7 +217,7 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
         runs.append({"U": U, "value": nx * ny * steps / (ms * 1e-3) / 1e6,
                      "ms_per_step": ms / steps,
                      "wall_stress_bottom_top": list(o["wall_stress"]),
-                     "mass_rel_drift": [abs(o["mass"][s] / (0.5 * nx * ny) - 1.0) for s in (0, 1)]})
+                     "mass_rel_drift": [abs(o["mass"][s] / m0[s] - 1.0) for s in (0, 1)]})
         lat.close()
         print(f"# couette {nx}x{ny} U={U}: {runs[-1]['value']:.0f} MLUPS", file=sys.stderr, flush=True)
     # reduced stress curve: `realizations` seeded channels per speed in one
@@ -243,20 +258,51 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
                               "points": curve}}
 
 
-def bench_precision(nx, ny, rho_a, rho_b, checkpoints=(1000, 5000, 10000, 20000)):
-    """FP32-deviation storage against FP64 storage on the full workload: max
-    |delta rho| and |delta u_phys| at each checkpoint, next to the FP64 twin
-    envelope (the same FP64 run started from rho_A perturbed by one ulp) and
-    an FP32-rounding twin (FP64 started from rho_A rounded to FP32)."""
+def _oracle_job(nx, ny, rho_a, rho_b, steps, out):
+    import oracle
+    p = oracle.Params(nx=nx, ny=ny, tau=PARAMS["tau"], rho0=PARAMS["rho0"], Ga=PARAMS["G_a"],
+                      Gr=PARAMS["G_r"], Gab=PARAMS["G_AB"])
+    t0 = time.perf_counter()
+    f, _ = oracle.run(p, oracle.init_equilibrium(p, rho_a, rho_b), steps)
+    fl = oracle.fields(p, f)
+    out.update(rho=fl["rho"], uphys=fl["uphys"], steps=steps, seconds=time.perf_counter() - t0,
+               threads=oracle.max_threads())
+
+
+def start_oracle(nx, ny, rho_a, rho_b, steps):
+    """The FP64 oracle on a workload for `steps` steps in a host thread (the
+    C library releases the interpreter while it runs), so GPU sections go on
+    meanwhile; join the thread before host-timed sections."""
+    import threading
+    out = {}
+    th = threading.Thread(target=_oracle_job, args=(nx, ny, rho_a, rho_b, steps, out), daemon=True)
+    th.start()
+    return th, out
+
+
+def bench_precision(nx, ny, rho_a, rho_b, oracle_job=None, checkpoints=(1000, 5000, 10000, 20000)):
+    """FP32-deviation storage on the full workload against GPU FP64 storage at
+    each checkpoint (max |delta rho|, max |delta u_phys|, the FP32 run's mass
+    drift from its own initial mass, I_AB and mean speed), next to two FP64
+    twins, the same FP64 run started (a) from rho_A perturbed by one ulp and
+    (b) from the initial populations each multiplied by an independent
+    1 + e, e uniform in [-2^-24, 2^-24): how far an FP32-level perturbation
+    of every site of both species grows by itself in these dynamics.  With
+    oracle_job (start_oracle on the same workload), both GPU storages are
+    also compared with the FP64 oracle at its step count."""
     import numpy as np
     from paper_0906_3611_amd import lb
-    runs = {}
-    starts = {"fp64": (rho_a, "fp64"), "fp32dev": (rho_a, "fp32dev"),
-              "twin_ulp": (np.nextafter(rho_a, 2.0), "fp64"),
-              "twin_f32": (rho_a.astype(np.float32).astype(np.float64), "fp64")}
-    for name, (ra, prec) in starts.items():
-        lat = lb.Lattice(nx, ny, precision=prec, **PARAMS)
-        lat.init(ra, rho_b)
+    runs, masses = {}, {}
+    for name in ("fp64", "fp32dev", "twin_ulp", "twin_noise"):
+        lat = lb.Lattice(nx, ny, precision="fp32dev" if name == "fp32dev" else "fp64", **PARAMS)
+        lat.init(np.nextafter(rho_a, 2.0) if name == "twin_ulp" else rho_a, rho_b)
+        if name == "twin_noise":
+            f0 = lat.populations()
+            rng = np.random.default_rng(20240)
+            f0 *= 1.0 + 2.0 ** -24 * (2.0 * rng.random(f0.shape) - 1.0)
+            lat.set_populations(f0, 0)
+            del f0
+        masses[name] = np.array(lat.observables()["mass"])
         out, done = [], 0
         for t in checkpoints:
             lat.step(t - done)
@@ -269,15 +315,28 @@ def bench_precision(nx, ny, rho_a, rho_b, checkpoints=(1000, 5000, 10000, 20000)
     for k, t in enumerate(checkpoints):
         ref_r, ref_u, ref_o = runs["fp64"][k]
         row = {"t": t}
-        for name in ("fp32dev", "twin_ulp", "twin_f32"):
+        for name in ("fp32dev", "twin_ulp", "twin_noise"):
             r, u, o = runs[name][k]
             row[name] = {"rho": float(np.abs(r - ref_r).max()), "u": float(np.abs(u - ref_u).max()),
-                         "mass_rel": float(np.abs(o["mass"] / ref_o["mass"] - 1).max()),
+                         "mass_rel_drift": float(np.abs(np.array(o["mass"]) / masses[name] - 1).max()),
                          "i_ab_rel": float(abs(o["i_ab"] / ref_o["i_ab"] - 1)),
                          "mean_speed_rel": float(np.mean(np.hypot(*u)) / np.mean(np.hypot(*ref_u)) - 1)}
+        row["fp64_mass_rel_drift"] = float(np.abs(np.array(ref_o["mass"]) / masses["fp64"] - 1).max())
         rows.append(row)
-    return {"workload": f"{nx}x{ny} disc emulsion as the headline run; GPU FP64 as reference",
-            "rows": rows}
+    res = {"workload": f"{nx}x{ny} disc emulsion (phi = 0.7, seed 2); GPU FP64 as reference",
+           "rows": rows}
+    if oracle_job is not None:
+        th, oj = oracle_job
+        th.join()
+        k = checkpoints.index(oj["steps"])
+        vs = {}
+        for name in ("fp32dev", "fp64", "twin_noise"):
+            r, u, _ = runs[name][k]
+            vs[name] = {"rho": float(np.abs(r - oj["rho"]).max()),
+                        "u": float(np.abs(u - oj["uphys"]).max())}
+        res["vs_oracle"] = {"t": oj["steps"], "oracle_seconds": oj["seconds"],
+                            "oracle_threads": oj["threads"], **vs}
+    return res
 
 
 def bench_kolmogorov(speeds=(0.005, 0.01, 0.02, 0.03, 0.04, 0.05), n=128,
@@ -316,9 +375,9 @@ def bench_ensemble(n_real=100, n=128, U0=0.02, steps=100000, every=10000, t_w=20
     realizations (noise seeds seed0 + i) of the 128^2 shear problem with the
     rho0 = 0.7 standard set, all in one batch.  Reports, every `every` steps,
     the mean and kurtosis of R(t) over realizations (Fig. 16), and the ageing
-    overlap C(t_w, dt_w) of Eq. (68) for t_w = 20000 (Fig. 12).  The paper runs
-    10^6 steps; this is the first 10^5."""
-    import numpy as np
+    overlap C(t_w, dt_w) of Eq. (68) for t_w = 20000 (Fig. 12) from the
+    per-lattice sums the device keeps against phi(t_w) (no fields leave the
+    GPU).  The paper runs 10^6 steps; this is the first 10^5."""
     from paper_0906_3611_amd import analysis, inputs, lb
     par = dict(tau=(1.0, 1.0), rho0=0.7, G_a=(-15.0, -14.0), G_r=(14.1, 13.1), G_AB=0.405)
     g = lb.kolmogorov_force(U0, n)
@@ -327,23 +386,22 @@ def bench_ensemble(n_real=100, n=128, U0=0.02, steps=100000, every=10000, t_w=20
         ra, rb = inputs.noise_fields(n, n, seed0 + i, 0.612, 0.612, 0.01)
         b.init(i, ra, rb)
     b.autotune(steps=20)
-
-    def phi_all():
-        return np.stack([analysis.order_parameter(b.fields(i)["rho"]) for i in range(n_real)])
-
-    rows, overlaps, done, ms, phi_w = [], [], 0, 0.0, None
+    rows, overlaps, done, ms, ref = [], [], 0, 0.0, False
     for t in range(every, steps + 1, every):
-        if phi_w is None and t > t_w:
+        if not ref and t > t_w:
             ms += _timed(b.stream, lambda: b.step(t_w - done))
             done = t_w
-            phi_w = phi_all()
+            b.set_overlap_reference()
+            ref = True
         ms += _timed(b.stream, lambda: b.step(t - done))
         done = t
-        R = analysis.response([o["u_mode"] for o in b.observables()], U0)
+        obs = b.observables()
+        R = analysis.response([o["u_mode"] for o in obs], U0)
         rows.append({"t": t, "R_mean": float(R.mean()), "R_std": float(R.std()),
                      "kurtosis": analysis.kurtosis(R)})
-        if phi_w is not None:
-            overlaps.append({"dt_w": t - t_w, "C": analysis.overlap(phi_w, phi_all())})
+        if ref:
+            overlaps.append({"dt_w": t - t_w, "C": sum(o["phi_overlap"] for o in obs)
+                             / sum(o["phi_ref_sq"] for o in obs)})
     b.close()
     return {"workload": f"{n_real} realizations {n}x{n} (seeds {seed0}..{seed0 + n_real - 1}), rho0 = 0.7 "
                         f"standard set, <rho> = 0.612 +- 0.01, U0 = {U0}, fp32dev, {steps} steps, one batch",
@@ -516,6 +574,39 @@ def service_times(trace, precision, timed_steps=100):
     return out
 
 
+def serve_fifo(trace, precision):
+    """A sequential server on the same GPU, run for real: jobs in arrival
+    order, one at a time, replayed in real time (a job starts once it has
+    arrived and the previous one has finished).  Each job creates its
+    lattice, initializes it, runs its steps and copies its observables and
+    density fields to the host; its time-to-result runs from its arrival to
+    that moment."""
+    from paper_0906_3611_amd import lb
+    t0 = time.perf_counter()
+    lat_s, t_report = [], time.perf_counter()
+    for k, j in enumerate(trace):
+        now = time.perf_counter() - t0
+        if now < j["t"]:
+            time.sleep(j["t"] - now)
+        if time.perf_counter() - t_report > 30.0:
+            print(f"# {precision} FIFO server: {k}/{len(trace)} jobs at {now:.0f} s",
+                  file=sys.stderr, flush=True)
+            t_report = time.perf_counter()
+        kw = _job_spec(j, precision)
+        nx, ny = kw.pop("nx"), kw.pop("ny")
+        lat = lb.Lattice(nx, ny, **kw)
+        lat.init_noise(j["seed"], 0.5, 0.5, 0.01)
+        lat.step(j["steps"])
+        lat.observables()
+        lat.fields()
+        lat.close()
+        lat_s.append(time.perf_counter() - t0 - j["t"])
+    makespan = time.perf_counter() - t0
+    work = sum(j["L"] ** 2 * j["steps"] for j in trace)
+    return {"jobs": len(trace), "precision": precision, "latency_s": _percentiles(lat_s),
+            "makespan_s": makespan, "value": work / makespan / 1e6, "site_updates": work}
+
+
 def fifo(trace, service):
     """First-in first-out single server: completion times and latencies."""
     end, lat = 0.0, []
@@ -527,15 +618,15 @@ def fifo(trace, service):
     return {"latency_s": _percentiles(lat), "makespan_s": span, "value": work / span / 1e6}
 
 
-def bench_serving(n_jobs=60, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5):
+def bench_serving(n_jobs=100, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5, lockstep=False):
     """Serving trace (Poisson arrivals, half Couette / half periodic, sides
     log-uniform in [64, 2048], steps log-uniform in [1e3, 5e4], FP32 storage)
-    replayed in real time against the pool (least-remaining-work schedule,
-    then again lock-step), then a rate-scaled variant at 0.7
-    of the capacity measured in the first replay.  Baselines: a sequential
-    first-in first-out server running one job at a time on the same GPU, in
-    FP64 and in FP32 storage, simulated from per-job service times measured
-    on this GPU."""
+    replayed in real time against the pool (least-remaining-work schedule;
+    with lockstep, again lock-step), then a rate-scaled variant at 0.7 of the
+    capacity measured in the first replay.  Baselines: a sequential
+    first-in first-out server running one job at a time on the same GPU in
+    FP64 storage, run for real on both traces; the same in FP32 storage
+    simulated from per-job service times measured on this GPU."""
     from paper_0906_3611_amd import inputs
     budget = int(budget_gb * (1 << 30))
     tr = inputs.serving_trace(n_jobs, rate, seed)
@@ -546,13 +637,18 @@ def bench_serving(n_jobs=60, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5):
     out = {"workload": f"{n_jobs} Poisson arrivals at {rate}/s (seed {seed}), 50/50 Couette/periodic, "
                        f"sides 64-2048, 1e3-5e4 steps, fp32dev, HBM budget {budget_gb} GiB",
            "served": served}
-    lock = replay_trace(tr, budget, schedule="lockstep")
-    print(f"# same trace, lock-step pool: {lock['value']:.0f} MLUPS, "
-          f"p50 {lock['latency_s']['p50']:.2f} s p99 {lock['latency_s']['p99']:.2f} s",
+    if lockstep:
+        lock = replay_trace(tr, budget, schedule="lockstep")
+        print(f"# same trace, lock-step pool: {lock['value']:.0f} MLUPS, "
+              f"p50 {lock['latency_s']['p50']:.2f} s p99 {lock['latency_s']['p99']:.2f} s",
+              file=sys.stderr, flush=True)
+        out["served_lockstep"] = lock
+    f64 = serve_fifo(tr, "fp64")
+    print(f"# same trace, sequential FP64 server: {f64['value']:.0f} MLUPS, "
+          f"p50 {f64['latency_s']['p50']:.2f} s p99 {f64['latency_s']['p99']:.2f} s",
           file=sys.stderr, flush=True)
-    out.update({"served_lockstep": lock,
-           "fifo_fp64": fifo(tr, service_times(tr, "fp64")),
-           "fifo_fp32dev": fifo(tr, service_times(tr, "fp32dev"))})
+    out["fifo_fp64"] = f64
+    out["fifo_fp32dev_simulated"] = fifo(tr, service_times(tr, "fp32dev"))
     if n_scaled:
         mean_work = sum(j["L"] ** 2 * j["steps"] for j in tr) / len(tr)
         cap_rate = served["value"] * 1e6 / mean_work  # jobs/s at the measured throughput
@@ -560,27 +656,33 @@ def bench_serving(n_jobs=60, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5):
         tr2 = inputs.serving_trace(n_scaled, rate2, seed + 1)
         s2 = replay_trace(tr2, budget)
         out["scaled_0p7"] = {"rate": rate2, "jobs": n_scaled, "served": s2,
-                             "fifo_fp64": fifo(tr2, service_times(tr2, "fp64"))}
+                             "fifo_fp64": serve_fifo(tr2, "fp64")}
         print(f"# scaled trace at {rate2:.2f}/s: p50 {s2['latency_s']['p50']:.2f} s "
-              f"p99 {s2['latency_s']['p99']:.2f} s", file=sys.stderr, flush=True)
+              f"p99 {s2['latency_s']['p99']:.2f} s; FIFO FP64 p50 "
+              f"{out['scaled_0p7']['fifo_fp64']['latency_s']['p50']:.2f} s",
+              file=sys.stderr, flush=True)
     return out
 
 
-def traffic_for(precision, sites):
+def traffic_key(precision, sites, walls=False):
+    return f"{precision}{'-couette' if walls else ''}@{sites}"
+
+
+def traffic_for(precision, sites, walls=False):
     """HBM bytes per step launch measured with rocprofv3 counters (scaled by
     a plain copy of known size), if they were taken on the current kernel."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
-    ent = rec.get(f"{precision}@{sites}")
+    ent = rec.get(traffic_key(precision, sites, walls))
     if not ent or ent.get("kernel_sha256_16") != kernel_hash(precision):
         return None
     return ent["bytes_per_launch"]
 
 
 def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv,
-                    copy_bytes=1 << 30):
+                    copy_bytes=1 << 30, walls=False):
     """Turn rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE counter CSVs into HBM
     bytes per step launch.  Each counter is scaled by what it reads for a
     plain copy of copy_bytes (the --copy-probe run), and the result is stored
@@ -599,7 +701,7 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
     # (name, template arguments, index and value of the argument that selects
     # periodic step launches)
     kname, nargs, at, val = {"fp32mom": ("k_mstep<", 1, None, None),
-                             "fp32dev": ("k_split<", 6, 3, "false"),    # WALLS
+                             "fp32dev": ("k_split<", 6, 3, "true" if walls else "false"),  # WALLS
                              "fp64": ("k_march<", 7, 4, "0")}[precision]  # MODE
 
     def step(n):
@@ -617,14 +719,56 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
     rec.pop("kernel_sha256_16", None)  # older single-hash format
-    rec[f"{precision}@{sites}"] = {"kernel_sha256_16": kernel_hash(precision),
+    key = traffic_key(precision, sites, walls)
+    rec[key] = {"kernel_sha256_16": kernel_hash(precision),
                       "sites": sites, "bytes_per_launch": fetch + write, "fetch_bytes": fetch,
                       "write_bytes": write, "fetch_scale": f_scale, "write_scale": w_scale,
                       "algorithmic_bytes": BYTES_PER_SITE[precision] * sites}
     os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(rec, fh, indent=1)
-    print(json.dumps(rec[f"{precision}@{sites}"]))
+    print(json.dumps(rec[key]))
+
+
+def hbm_ceiling(nbytes: int, reps: int = 5) -> dict:
+    """Practical ceiling of a kernel that reads nbytes / 2 and writes nbytes / 2
+    once each (the budget of one step): the hand-written dwordx4 copy of
+    libhbmprobe (include/hbm_probe.h), swept over the grid (workgroups of 256
+    lanes per CU), the 16-byte items in flight per lane and plain /
+    nontemporal stores; the fastest, in GB/s of bytes read plus written,
+    with the sweep's best five."""
+    import ctypes
+    import torch
+    from paper_0906_3611_amd import _build
+    L = ctypes.CDLL(_build.PROBE_LIB)
+    L.hbm_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    L.hbm_copy.restype = ctypes.c_int
+    half = (nbytes // 2) // 4096 * 4096
+    a = torch.ones(half // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    res = []
+    for wg_per_cu in (1, 2, 4, 8, 16, 32):
+        for unroll in (1, 2, 4):
+            for nt in (0, 1):
+                blocks = wg_per_cu * cus
+
+                def go():
+                    if L.hbm_copy(a.data_ptr(), b.data_ptr(), half, blocks, 256, nt, unroll,
+                                  st.cuda_stream) != 0:
+                        raise RuntimeError("hbm_copy refused its arguments")
+                go()
+                go()
+                ms = _timed(st, lambda: [go() for _ in range(reps)]) / reps
+                res.append({"workgroups_per_cu": wg_per_cu, "unroll": unroll, "nt": nt,
+                            "gbs": 2.0 * half / (ms * 1e-3) / 1e9})
+    del a, b
+    torch.cuda.empty_cache()
+    res.sort(key=lambda r: -r["gbs"])
+    return {"ceiling_gbs": res[0]["gbs"], "bytes_per_copy": 2 * half, "best": res[0],
+            "top5": res[:5], "configs": len(res)}
 
 
 def device_copy_gbs(nbytes: int, reps: int = 20) -> float:
@@ -655,39 +799,77 @@ def copy_probe(mib: int = 1024, reps: int = 5):
     print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "reps": reps}))
 
 
+def _roofline(run, precision, sites, walls, ceiling):
+    """The roofline record of a step kernel's run: achieved = algorithmic
+    bytes per launch (bytes per site update x sites) / average launch time
+    (HIP events over the timed region, on the library's stream)."""
+    pop_bytes = BYTES_PER_SITE[precision] * sites  # both population buffers (half each)
+    rec = {"bound": "hbm", "achieved": run["achieved_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": run["achieved_gbs"] / PEAK_HBM_GBS,
+           "traffic": traffic_for(precision, sites, walls),
+           "kernel": STEP_KERNEL[precision] + (" (walls)" if walls else ""),
+           "bytes_per_site": BYTES_PER_SITE[precision], "units_per_launch": sites,
+           # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed
+           "cache_resident": pop_bytes <= (256 << 20)}
+    if ceiling:
+        rec["ceiling_gbs"] = ceiling["ceiling_gbs"]
+        rec["frac_of_ceiling"] = run["achieved_gbs"] / ceiling["ceiling_gbs"]
+        rec["ceiling_probe"] = ceiling["best"]
+    return rec
+
+
+def _summary(run, precision, sites, walls, ceiling):
+    return {"value": run["mlups"], "ms_per_step": run["ms_per_step"],
+            "achieved_gbs": run["achieved_gbs"], "frac": run["achieved_gbs"] / PEAK_HBM_GBS,
+            "roofline": _roofline(run, precision, sites, walls, ceiling), "launch": run["info"],
+            "mass_rel_drift": run["mass_rel_drift"]}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--nx", type=int, default=1024)
-    ap.add_argument("--ny", type=int, default=1024)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--tune-steps", type=int, default=20,
+                    help="timed steps per candidate when autotuning the headline lattice (0: no tuning)")
+    ap.add_argument("--workload", choices=["c3", "c2", "p4096x1024", "p4096x4096"], default="c3",
+                    help="headline: c3, the 4096x1024 Couette channel (HBM-resident); c2, the "
+                         "1024^2 periodic disc emulsion (cache-resident in FP32); p4096x1024 and "
+                         "p4096x4096, the periodic HBM-resident probes (mixture 0.5 +- 0.01)")
     ap.add_argument("--precision", choices=["fp32dev", "fp64", "fp32mom"], default="fp32dev")
-    ap.add_argument("--boundary", choices=["periodic", "couette"], default="periodic",
-                    help="main run only (couette: walls on y moving at -/+ --u-wall)")
-    ap.add_argument("--u-wall", type=float, default=0.005)
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage companion run")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline run, its copy ceiling and the CPU baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-storage runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-probe", action="store_true", help="skip the 4096x1024 HBM-resident probe")
+    ap.add_argument("--no-probe", action="store_true", help="skip the other HBM-resident shapes")
     ap.add_argument("--copy-probe", action="store_true", help="only run a plain 1 GiB copy")
     ap.add_argument("--no-couette", action="store_true", help="skip the Couette channel runs")
     ap.add_argument("--no-kolmogorov", action="store_true", help="skip the shear-forcing protocol")
-    ap.add_argument("--no-precision", action="store_true", help="skip the FP32-vs-FP64 error study")
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the FP32-vs-FP64 error study (and its oracle run)")
+    ap.add_argument("--precision-oracle-steps", type=int, default=1000,
+                    help="steps of the FP64 oracle on the 1024^2 workload (0: none)")
     ap.add_argument("--no-moment", action="store_true", help="skip the tau = 1 moment-storage runs")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 100-realization ensemble")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--ensemble", type=int, default=256, help="lattices in the batched ensemble")
     ap.add_argument("--ensemble-steps", type=int, default=5000)
-    ap.add_argument("--serve-jobs", type=int, default=60, help="arrivals in the serving trace")
+    ap.add_argument("--serve-jobs", type=int, default=100, help="arrivals in the serving trace")
     ap.add_argument("--serve-scaled-jobs", type=int, default=30,
                     help="arrivals in the 0.7x-capacity trace (0: skip)")
+    ap.add_argument("--serve-lockstep", action="store_true",
+                    help="also replay the trace with the lock-step pool schedule")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
-                    help="store HBM traffic per step from rocprofv3 counter CSVs and exit")
+                    help="store HBM traffic per step from rocprofv3 counter CSVs and exit "
+                         "(for the --workload and --precision given)")
     args = ap.parse_args()
+    c3 = args.workload == "c3"
+    nx, ny = {"c3": (4096, 1024), "c2": (1024, 1024), "p4096x1024": (4096, 1024),
+              "p4096x4096": (4096, 4096)}[args.workload]
     if args.ingest_counters:
-        ingest_counters(args.precision, args.nx * args.ny, *args.ingest_counters)
+        ingest_counters(args.precision, nx * ny, *args.ingest_counters, walls=c3)
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -707,50 +889,69 @@ def main():
     from paper_0906_3611_amd import inputs
     import numpy as np
 
-    nx, ny = args.nx, args.ny
-    rho_a, rho_b = inputs.disc_fields(nx, ny, seed=2, phi=0.7)
-    walls = args.boundary == "couette"
-    if walls and args.precision == "fp32mom":
+    if c3 and args.precision == "fp32mom":
         print("the moment storage is periodic only", file=sys.stderr)
         sys.exit(2)
+    # the headline workload
+    if c3:
+        rho_a, rho_b = inputs.noise_fields(nx, ny, 3, 0.5, 0.5, 0.01)
+        label = (f"{nx}x{ny} planar Couette channel (walls at -/+{HEADLINE_U} on y, periodic x), "
+                 f"mixture 0.5 +- 0.01 (seed 3)")
+    elif args.workload == "c2":
+        rho_a, rho_b = inputs.disc_fields(nx, ny, seed=2, phi=0.7)
+        label = f"{nx}x{ny} periodic, seeded disc emulsion phi=0.7"
+    else:
+        rho_a, rho_b = inputs.noise_fields(nx, ny, 3, 0.5, 0.5, 0.01)
+        label = f"{nx}x{ny} periodic, mixture 0.5 +- 0.01 (seed 3)"
+    sites = nx * ny
+    # the copy ceiling first: its sweep also brings the GPU out of idle, so
+    # the headline's short timed region runs at steady clocks
+    ceiling = hbm_ceiling(BYTES_PER_SITE[args.precision] * sites)
+    print(f"# copy ceiling for {BYTES_PER_SITE[args.precision] * sites / 1e6:.0f} MB: "
+          f"{ceiling['ceiling_gbs']:.0f} GB/s", file=sys.stderr, flush=True)
+    # the autotuner picks the launch shape on the headline lattice's own
+    # state (and restores it), right before the warmup and the timed steps
     main_run = run_gpu(nx, ny, args.precision, args.steps, args.warmup, rho_a, rho_b,
-                       args.boundary, args.u_wall if walls else 0.0)
-    print(f"# {args.precision} {nx}x{ny}: {main_run['mlups']:.0f} MLUPS, "
+                       "couette" if c3 else "periodic", HEADLINE_U if c3 else 0.0,
+                       tune_steps=args.tune_steps)
+    print(f"# headline {args.precision} {label}: {main_run['mlups']:.0f} MLUPS, "
           f"{main_run['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
+    # the oracle on the 1024^2 emulsion runs on the host while the GPU sections go on
+    full = not args.headline_only
+    c2a, c2b = inputs.disc_fields(1024, 1024, seed=2, phi=0.7)
+    oracle_job = None
+    if full and not args.no_precision and args.precision_oracle_steps > 0:
+        oracle_job = start_oracle(1024, 1024, c2a, c2b, args.precision_oracle_steps)
 
     extra = {}
-    r64 = None
-    if not args.no_fp64 and args.precision != "fp64":
-        r64 = run_gpu(nx, ny, "fp64", args.steps, args.warmup, rho_a, rho_b)
-        extra["fp64"] = {"value": r64["mlups"], "ms_per_step": r64["ms_per_step"],
-                         "achieved_gbs": r64["achieved_gbs"],
-                         "roofline_frac": r64["achieved_gbs"] / PEAK_HBM_GBS}
-        extra["fp32dev_vs_fp64_max_abs_rho"] = float(np.abs(main_run["rho"] - r64["rho"]).max())
-        print(f"# fp64 {nx}x{ny}: {r64['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-    if not args.no_probe:
-        # HBM-resident shape (4096 x 1024, 604 MB of FP32 populations): larger
-        # than the 256 MB Infinity Cache, unlike the 1024^2 workload.
-        pa, pb = inputs.noise_fields(4096, 1024, 3, 0.5, 0.5, 0.01)
-        pr = run_gpu(4096, 1024, args.precision, 2000, 100, pa, pb)
-        cp = device_copy_gbs(BYTES_PER_SITE[args.precision] * 4096 * 1024)
-        extra["hbm_probe_4096x1024"] = {"value": pr["mlups"], "ms_per_step": pr["ms_per_step"],
-                                        "achieved_gbs": pr["achieved_gbs"],
-                                        "frac": pr["achieved_gbs"] / PEAK_HBM_GBS,
-                                        "device_copy_gbs": cp,
-                                        "frac_of_device_copy": pr["achieved_gbs"] / cp,
-                                        "traffic": traffic_for(args.precision, 4096 * 1024)}
-        print(f"# probe 4096x1024: {pr['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-        # 4096^2 (2.4 GB of FP32 populations)
-        qa, qb = inputs.noise_fields(4096, 4096, 3, 0.5, 0.5, 0.01)
-        pq = run_gpu(4096, 4096, args.precision, 400, 20, qa, qb)
-        cq = device_copy_gbs(BYTES_PER_SITE[args.precision] * 4096 * 4096)
-        extra["hbm_probe_4096x4096"] = {"value": pq["mlups"], "ms_per_step": pq["ms_per_step"],
-                                        "achieved_gbs": pq["achieved_gbs"],
-                                        "frac": pq["achieved_gbs"] / PEAK_HBM_GBS,
-                                        "device_copy_gbs": cq,
-                                        "frac_of_device_copy": pq["achieved_gbs"] / cq,
-                                        "traffic": traffic_for(args.precision, 4096 * 4096)}
-        print(f"# probe 4096x4096: {pq['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    r2 = None  # the 1024^2 emulsion, 20000 steps after 200 (the moment storage compares with it)
+    if full:
+        r2 = run_gpu(1024, 1024, "fp32dev", 20000, 200, c2a, c2b)
+        cc = hbm_ceiling(BYTES_PER_SITE["fp32dev"] * 1024 * 1024)
+        extra["c2_1024x1024"] = dict(
+            _summary(r2, "fp32dev", 1024 * 1024, False, cc),
+            workload="1024x1024 periodic disc emulsion phi=0.7 (seed 2), fp32dev, cache-resident")
+        print(f"# c2 1024^2: {r2['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    if full and not args.no_fp64 and args.precision != "fp64":
+        f64 = {}
+        for (fx, fy, init, n_steps) in ((1024, 1024, (c2a, c2b), 4000),
+                                       (4096, 1024, inputs.noise_fields(4096, 1024, 3, 0.5, 0.5, 0.01),
+                                        2000)):
+            r = run_gpu(fx, fy, "fp64", n_steps, 100, *init)
+            f64[f"{fx}x{fy}"] = {"value": r["mlups"], "ms_per_step": r["ms_per_step"],
+                                 "achieved_gbs": r["achieved_gbs"],
+                                 "frac": r["achieved_gbs"] / PEAK_HBM_GBS, "launch": r["info"]}
+            print(f"# fp64 {fx}x{fy}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        extra["fp64"] = f64
+    if full and not args.no_probe:
+        # HBM-resident periodic shapes: 4096 x 1024 (604 MB of FP32 populations)
+        # and the graded 4096^2 probe (2.4 GB)
+        for (px, py, n_steps) in ((4096, 1024, 2000), (4096, 4096, 400)):
+            pa, pb = inputs.noise_fields(px, py, 3, 0.5, 0.5, 0.01)
+            pr = run_gpu(px, py, args.precision, n_steps, 20, pa, pb)
+            pc = hbm_ceiling(BYTES_PER_SITE[args.precision] * px * py)
+            extra[f"hbm_probe_{px}x{py}"] = _summary(pr, args.precision, px * py, False, pc)
+            print(f"# probe {px}x{py}: {pr['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         # one GPU's share of a y-slab decomposition of a 4096-wide channel over 8
         # GPUs: 128 owned rows plus the 3 ghost rows per side a step would need
         sa, sb = inputs.noise_fields(4096, 134, 3, 0.5, 0.5, 0.01)
@@ -758,46 +959,30 @@ def main():
         extra["slab_share_4096x134"] = {"value": ps["mlups"], "us_per_step": ps["ms_per_step"] * 1e3,
                                         "owned_rows": 128, "ghost_rows_per_side": 3,
                                         "achieved_gbs": ps["achieved_gbs"]}
-        print(f"# slab share 4096x134: {ps['ms_per_step'] * 1e3:.1f} us/step", file=sys.stderr,
+    if full and not args.no_moment and args.precision != "fp32mom":
+        extra["moment_tau1"] = bench_moment(1024, 1024, 20000, 200, c2a, c2b, r2, None,
+                                            args.no_probe)
+        print(f"# fp32mom 1024^2: {extra['moment_tau1']['value']:.0f} MLUPS", file=sys.stderr,
               flush=True)
-
-    if not args.no_moment and args.precision != "fp32mom":
-        extra["moment_tau1"] = bench_moment(nx, ny, args.steps, args.warmup, rho_a, rho_b,
-                                            main_run, r64, args.no_probe)
-        print(f"# fp32mom {nx}x{ny}: {extra['moment_tau1']['value']:.0f} MLUPS", file=sys.stderr,
-              flush=True)
-    if not args.no_precision and (nx, ny) == (1024, 1024):
-        extra["precision_c2"] = bench_precision(nx, ny, rho_a, rho_b)
-        print("# precision study done", file=sys.stderr, flush=True)
-    if not args.no_couette:
+    if full and not args.no_couette:
         extra["couette"] = bench_couette()
-    if not args.no_kolmogorov:
+    if full and not args.no_batch:
+        extra["batched_ensemble"] = bench_batch(args.ensemble, args.ensemble_steps)
+    if full and not args.no_precision:
+        extra["precision_c2"] = bench_precision(1024, 1024, c2a, c2b, oracle_job)
+        print("# precision study done", file=sys.stderr, flush=True)
+    if full and not args.no_kolmogorov:
         extra["kolmogorov"] = bench_kolmogorov()
         print(f"# kolmogorov batch: {extra['kolmogorov']['value']:.0f} MLUPS", file=sys.stderr,
               flush=True)
-    if not args.no_ensemble:
+    if full and not args.no_ensemble:
         extra["shear_ensemble"] = bench_ensemble()
         print(f"# shear ensemble: {extra['shear_ensemble']['value']:.0f} MLUPS", file=sys.stderr,
               flush=True)
-    if not args.no_batch:
-        extra["batched_ensemble"] = bench_batch(args.ensemble, args.ensemble_steps)
-    if not args.no_serve:
+    if full and not args.no_serve:
         extra["serving"] = bench_serving(args.serve_jobs, 50.0, args.serve_scaled_jobs,
-                                         args.serve_budget_gb)
+                                         args.serve_budget_gb, lockstep=args.serve_lockstep)
 
-    sites = nx * ny
-    pop_bytes = BYTES_PER_SITE[args.precision] * sites  # both population buffers (half each)
-    roof = {"bound": "hbm", "achieved": main_run["achieved_gbs"], "peak": PEAK_HBM_GBS,
-            "unit": "GB/s", "frac": main_run["achieved_gbs"] / PEAK_HBM_GBS,
-            "traffic": None if walls else traffic_for(args.precision, sites),
-            "kernel": STEP_KERNEL[args.precision] + (" (walls)" if walls else ""),
-            "bytes_per_site": BYTES_PER_SITE[args.precision],
-            "units_per_launch": sites,
-            # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed
-            "cache_resident": pop_bytes <= (256 << 20)}
-    # context: a plain device copy of the same bytes on this GPU
-    roof["device_copy_gbs"] = device_copy_gbs(pop_bytes)
-    roof["frac_of_device_copy"] = main_run["achieved_gbs"] / roof["device_copy_gbs"]
     line = {
         "metric": "two-species MLUPS",
         "value": main_run["mlups"],
@@ -808,22 +993,26 @@ def main():
         "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": main_run["mlups"] / PAPER_MLUPS,
+        # the paper's only figure is for another workload (1024^2) on another GPU
+        "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{nx}x{ny} "
-                               + (f"Couette (walls at -/+{args.u_wall})" if walls else "periodic")
-                               + f" two-species Shan-Chen D2Q9, seeded disc "
-                               f"emulsion phi=0.7, rho0=0.83 standard couplings, "
+        "config": {"workload": f"{label}, two-species Shan-Chen D2Q9, rho0=0.83 standard couplings, "
                                f"{args.precision} storage",
                    "nx": nx, "ny": ny, "precision": args.precision,
-                   "launch": main_run["info"]},
-        "roofline": roof,
-        "mass": list(main_run["obs"]["mass"]),
+                   "boundary": "couette" if c3 else "periodic", "u_wall": HEADLINE_U if c3 else 0.0,
+                   "launch": main_run["info"], "autotune": main_run.get("autotune")},
+        "roofline": _roofline(main_run, args.precision, sites, c3, ceiling),
+        "hbm_ceiling": ceiling,
+        "mass_rel_drift": main_run["mass_rel_drift"],
+        "paper_context": {"mlups": PAPER_MLUPS, "workload": "1024^2, 10^6 steps in about one day",
+                          "hardware": "GPU not named", "source": "Appendix"},
     }
     line.update(extra)
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(nx, ny, rho_a, rho_b)
+        line["cpu_baseline"] = cpu_baseline(nx, ny, rho_a, rho_b, walls=c3,
+                                            u_wall=HEADLINE_U if c3 else 0.0, label=label)
+        line["vs_cpu_baseline"] = main_run["mlups"] / line["cpu_baseline"]["value"]
     print(json.dumps(line), flush=True)
 
 

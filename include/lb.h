@@ -270,12 +270,24 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
  * the lattice's stream.  Results are kept for the life of the process, by
  * GPU architecture, precision, boundary type, graph use and lattice shapes;
  * steps = 0 applies a kept result without timing anything (and tunes with 16
- * steps when there is none).  The device state (populations, wall links, flags)
+ * steps when there is none; lb_set_tune_cache keeps results across
+ * processes).  The device state (populations, wall links, flags)
  * and the step count are copied aside first and restored, so the evolution
  * and the wall-stress averages are unchanged.  Needs temporary device memory of the lattice's workspace size
  * (LB_E_NOMEM otherwise).  out (may be NULL) receives the chosen shape,
  * us_per_step (may be NULL) its time per step.  Synchronous. */
 int lb_autotune(lb_lattice* lat, int32_t steps, lb_launch_info* out, double* us_per_step);
+
+/* Keep the autotuner's results (lb_autotune, lb_batch_autotune) in the text
+ * file `path` as well: results already in it are loaded now (lines that do
+ * not parse are skipped), and the whole table is written back, through a
+ * temporary file renamed into place, after every new result, so a later
+ * process can apply them with steps = 0.  Keys carry the ABI version, GPU
+ * architecture, storage, boundary type, graph use and lattice shapes; a
+ * result only picks among launch shapes that give bit-identical numbers.
+ * NULL or "" stops writing.  LB_E_INVAL if the file cannot be written.
+ * Thread-safe; host only. */
+int lb_set_tune_cache(const char* path);
 
 void lb_destroy(lb_lattice* lat);
 const char* lb_strerror(int status);

@@ -121,6 +121,8 @@ int engine_regrid(Engine& E, int seg_h);
 // fastest; the state and step count are restored.  *us_per_step (may be
 // NULL) receives the chosen shape's time per step.
 int engine_autotune(Engine& E, int steps, double* us_per_step);
+// Persist autotuner results in a text file (see lb_set_tune_cache).
+int set_tune_cache(const char* path);
 void engine_info(const Engine& E, lb_launch_info* out);
 int64_t member_time(const Engine& E, int i);
 int member_index(const Engine& E, int64_t tag);

@@ -6,9 +6,12 @@
 #include <array>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
+#include <sstream>
 
 namespace lbe {
 static_assert(lbk::kNRed + 2 <= 16, "reduction output rows hold 16 doubles");
@@ -295,13 +298,16 @@ int retile(Engine& E) {
 
 void choose_default_variant(Engine& E) {
   // Defaults (measured): streaming stores when the population buffers
-  // exceed the 256 MB Infinity Cache.  FP32 (one wave per species, four per
-  // SIMD): no prefetch.  FP64 (one wave per SIMD): a one-row prefetch.
+  // exceed the 256 MB Infinity Cache.  A one-row prefetch for the
+  // population storages: FP32 deviations (one wave per species) step 1.6-3.7%
+  // faster with it than without at 1024^2 to 4096^2, periodic and with walls
+  // (with walls it costs no occupancy: 124 against 109 VGPRs, four waves per
+  // SIMD either way); FP64 (one wave per SIMD) likewise.
   if (E.variant_forced) return;
   size_t total_pop = 0;
   for (auto& mm : E.m) total_pop += 2 * mm.pop_bytes;
   const bool hbm = total_pop > kInfinityCacheBytes;
-  E.variant.prefetch = split_kernel(E) ? 0 : ((E.fp64 || !hbm) ? 1 : 0);
+  E.variant.prefetch = (E.mom && hbm) ? 0 : 1;
   E.variant.stream_stores = hbm ? 1 : 0;
 }
 
@@ -985,8 +991,12 @@ std::vector<int> seg_signature(const Engine& E, int seg_h) {
 // end, so the state, the wall-stress averages included, is unchanged.
 namespace {
 
-// Autotuner results of this process, by GPU architecture, precision,
-// boundary type, graph use and the members' shapes.
+// Autotuner results, by library ABI, GPU architecture, storage, boundary
+// type, graph use and the members' shapes: kept for the life of the
+// process and, after lb_set_tune_cache, in a text file (one result per
+// line: key, segment height, prefetch, streaming stores, us per step).  A
+// result only selects among launch shapes that give the same numbers bit
+// for bit, so a stale one costs speed, never correctness.
 struct TuneResult {
   int seg_h;
   lbk::StepVariant v;
@@ -994,17 +1004,55 @@ struct TuneResult {
 };
 std::mutex g_tune_mu;
 std::map<std::string, TuneResult> g_tune_cache;
+std::string g_tune_path;  // "" = not persisted
 
 std::string tune_key(const Engine& E) {
   hipDeviceProp_t prop{};
   std::string arch = hipGetDeviceProperties(&prop, E.device) == hipSuccess ? prop.gcnArchName : "?";
+  // the architecture name may carry feature flags (gfx950:sramecc+:xnack-)
+  for (char& ch : arch)
+    if (ch == ' ') ch = '_';
   std::vector<std::pair<int, int>> shapes;
   for (const auto& mm : E.m) shapes.emplace_back(mm.p.nx, mm.p.ny);
   std::sort(shapes.begin(), shapes.end());
-  std::string k = arch + (E.fp64 ? "/f64" : "/f32") + (E.walls ? "/walls" : "/periodic") +
-                  (E.use_graph ? "/graph" : "/launch");
+  std::string k = "abi" + std::to_string(LB_ABI_VERSION) + "/" + arch +
+                  (E.fp64 ? "/f64" : (E.mom ? "/f32mom" : "/f32dev")) +
+                  (E.walls ? "/walls" : "/periodic") + (E.use_graph ? "/graph" : "/launch");
   for (auto& s : shapes) k += "/" + std::to_string(s.first) + "x" + std::to_string(s.second);
   return k;
+}
+
+// Caller holds g_tune_mu.  Lines that do not parse or hold values out of
+// range are skipped.
+void load_tune_file(const std::string& path) {
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string key;
+    TuneResult r{};
+    if (!(ls >> key >> r.seg_h >> r.v.prefetch >> r.v.stream_stores >> r.us)) continue;
+    if (r.seg_h < 0 || r.v.prefetch < 0 || r.v.prefetch > 2 || (r.v.stream_stores & ~1) ||
+        !(r.us > 0.0))
+      continue;
+    g_tune_cache[key] = r;
+  }
+}
+
+// Caller holds g_tune_mu.  Writes the whole cache next to the file and
+// renames it into place, so a reader never sees half a file.
+bool save_tune_file(const std::string& path) {
+  const std::string tmp = path + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    if (!out) return false;
+    out.precision(17);  // times round-trip
+    for (const auto& kv : g_tune_cache)
+      out << kv.first << ' ' << kv.second.seg_h << ' ' << kv.second.v.prefetch << ' '
+          << kv.second.v.stream_stores << ' ' << kv.second.us << '\n';
+    if (!out) return false;
+  }
+  return std::rename(tmp.c_str(), path.c_str()) == 0;
 }
 
 }  // namespace
@@ -1140,9 +1188,22 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune_cache[key] = TuneResult{best_h, best_v, best};
+    if (!g_tune_path.empty() && !save_tune_file(g_tune_path))
+      E.err = "autotune result kept, but writing " + g_tune_path + " failed";
   }
   if (us_per_step) *us_per_step = best;
   return LB_OK;
+}
+
+int set_tune_cache(const char* path) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (!path || !*path) {
+    g_tune_path.clear();
+    return LB_OK;
+  }
+  g_tune_path = path;
+  load_tune_file(g_tune_path);
+  return save_tune_file(g_tune_path) ? LB_OK : LB_E_INVAL;
 }
 
 void engine_info(const Engine& E, lb_launch_info* out) {

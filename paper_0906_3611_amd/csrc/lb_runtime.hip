@@ -78,6 +78,8 @@ int lb_create(const lb_params* p, void* hip_stream, lb_lattice** out) {
   return LB_OK;
 }
 
+int lb_set_tune_cache(const char* path) { return lbe::set_tune_cache(path); }
+
 void lb_destroy(lb_lattice* L) {
   if (!L) return;
   lbe::engine_destroy(L->e);

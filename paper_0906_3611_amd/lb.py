@@ -115,6 +115,7 @@ def load():
         "lb_batch_set_launch": ([h, i32, i32, i32, i32], ctypes.c_int),
         "lb_batch_autotune": ([h, i32, P(lb_launch_info), dp], ctypes.c_int),
         "lb_autotune": ([h, i32, P(lb_launch_info), dp], ctypes.c_int),
+        "lb_set_tune_cache": ([ctypes.c_char_p], ctypes.c_int),
         "lb_batch_destroy": ([h], None),
         "lb_batch_last_error": ([h], ctypes.c_char_p),
     }
@@ -188,6 +189,14 @@ def make_params(nx, ny, *, tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0), G_r=(8.1
     p.body_force_x = body_force_x
     p.rho_ref[0], p.rho_ref[1] = rho_ref
     return p
+
+
+def set_tune_cache(path):
+    """Persist autotuner results in a text file (lb_set_tune_cache); None stops."""
+    L = load()
+    rc = L.lb_set_tune_cache(None if path is None else os.fsencode(path))
+    if rc != 0:
+        raise LBError(rc, f"lb_set_tune_cache: cannot write {path}")
 
 
 def kolmogorov_force(U0, ny, tau=1.0):

@@ -120,3 +120,42 @@ def test_library_disc_fields_reject_bad_specs(L):
 def test_pool_schedule_names_checked_before_any_device_call():
     with pytest.raises(ValueError):
         lb.Pool(1 << 20, schedule="fifo")
+
+
+def test_tune_cache_file_is_loaded_filtered_and_rewritten(L, tmp_path):
+    """lb_set_tune_cache reads a results file (skipping lines that do not
+    parse or hold out-of-range values) and writes the table back whole."""
+    path = tmp_path / "tune.txt"
+    path.write_text("abi3/gfx950/f32dev/periodic/launch/64x64 8 0 1 12.5\n"
+                    "garbage line\n"
+                    "abi3/gfx950/f64/walls/launch/70x45 16 7 0 30.0\n"   # prefetch out of range
+                    "abi3/gfx950/f32mom/periodic/launch/128x128 4 0 0 9.0\n")
+    assert L.lb_set_tune_cache(str(path).encode()) == lb.LB_OK
+    lines = sorted(path.read_text().splitlines())
+    assert lines == ["abi3/gfx950/f32dev/periodic/launch/64x64 8 0 1 12.5",
+                     "abi3/gfx950/f32mom/periodic/launch/128x128 4 0 0 9"]
+    assert L.lb_set_tune_cache(None) == lb.LB_OK
+    assert L.lb_set_tune_cache(str(tmp_path / "missing_dir" / "t.txt").encode()) == lb.LB_E_INVAL
+    assert L.lb_set_tune_cache(None) == lb.LB_OK
+
+
+def test_probe_library_exports_its_header():
+    """libhbmprobe.so (the copy-ceiling probe the benchmark runs) loads
+    without a GPU and exports every function include/hbm_probe.h declares;
+    invalid arguments are refused on the host before any launch."""
+    import re
+    from paper_0906_3611_amd import _build
+    assert os.path.exists(_build.PROBE_LIB), "libhbmprobe.so is not built"
+    P = ctypes.CDLL(_build.PROBE_LIB)
+    hdr = os.path.join(os.path.dirname(lb.HEADER), "hbm_probe.h")
+    txt = re.sub(r"/\*.*?\*/", "", open(hdr).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(hbm_[a-z_]+)\s*\(", txt)))
+    assert names == ["hbm_copy"]
+    for n in names:
+        assert hasattr(P, n), n
+    P.hbm_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    # null buffers, a size that is not a multiple of 16, a bad unroll: refused
+    assert P.hbm_copy(None, None, 4096, 1, 256, 0, 1, None) == -1
+    assert P.hbm_copy(16, 32, 100, 1, 256, 0, 1, None) == -1
+    assert P.hbm_copy(16, 32, 4096, 1, 256, 0, 3, None) == -1

@@ -283,3 +283,37 @@ def test_default_tile_policy(precision, nx, ny, seg_h):
     assert info["seg_h"] == seg_h, info
     assert info["ntiles"] == info["nstrips"] * info["nsegs"]
     lat.close()
+
+
+def test_autotune_result_persists_across_processes(tmp_path):
+    """With lb_set_tune_cache, a tuned result written by one process is
+    applied with steps = 0 (no timing) by another."""
+    import json
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    prog = r'''
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+from paper_0906_3611_amd import inputs, lb
+lb.set_tune_cache(sys.argv[2])
+lat = lb.Lattice(100, 70, precision="fp32dev", tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0),
+                 G_r=(8.1, 8.1), G_AB=0.405)
+lat.init(*inputs.noise_fields(100, 70, 5, 0.5, 0.5, 0.01))
+r = lat.autotune(steps=int(sys.argv[3]))
+print(json.dumps({k: r[k] for k in ("seg_h", "nsegs", "prefetch", "stream_stores", "us_per_step")}))
+'''
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+    def run(steps):
+        out = subprocess.run([sys.executable, "-c", prog, root, str(cache), str(steps)],
+                             capture_output=True, text=True, timeout=240)
+        assert out.returncode == 0, out.stderr[-2000:]
+        return json.loads(out.stdout.strip().splitlines()[-1])
+
+    first = run(8)
+    assert "/f32dev/periodic/launch/100x70 " in cache.read_text()
+    second = run(0)
+    assert second == first
