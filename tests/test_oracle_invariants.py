@@ -97,3 +97,21 @@ def test_species_swap_bitwise():
     g, _ = oracle.run(p, f, 30)
     gs, _ = oracle.run(p, f[::-1].copy(), 30)
     assert np.array_equal(g[::-1], gs)
+
+
+def test_equilibrium_moments():
+    """The second-order equilibrium (display below Eq. (1)) has the moments
+    rho, rho u and, off the diagonal, rho u_x u_y (the D2Q9 weights make
+    sum w c_x c_y = 0 and sum w c_x^2 c_y^2 = 1/9).  A random field of
+    densities and velocities, summed by the oracle's global sums."""
+    rng = np.random.default_rng(11)
+    ny, nx = 7, 9
+    p = oracle.Params(nx=nx, ny=ny, **C1)
+    ra, rb = 0.3 + rng.random((2, ny, nx))
+    ux, uy = 0.1 * (2 * rng.random((2, ny, nx)) - 1)
+    f = oracle.init_equilibrium(p, ra, rb, ux, uy)
+    t = oracle.totals(p, f)
+    assert t["mass"] == pytest.approx([ra.sum(), rb.sum()], rel=1e-14)
+    rho = ra + rb
+    assert t["mom"] == pytest.approx([(rho * ux).sum(), (rho * uy).sum()], rel=1e-12, abs=1e-15)
+    assert t["pxy_kin"] == pytest.approx((rho * ux * uy).sum(), rel=1e-12, abs=1e-15)

@@ -7,7 +7,8 @@
 * Single-phase limit: shear waves decay with nu = c_s^2 (tau - 1/2) (Sec. VI:
   tau = 1 <-> nu = 1/6), with the mixture relaxation time of the Sec. III
   footnote when tau_A != tau_B.
-* Couette flow between moving walls: linear profile and wall stress rho nu du/dy.
+* Couette flow between moving walls: linear profile, wall stress rho nu du/dy
+  and the pre-collision kinetic stress -tau rho c_s^2 du/dy.
 * Plane Poiseuille flow (a uniform body force between walls at rest): the
   closed-form steady state of BGK with halfway bounce-back, a parabola with
   a uniform slip g (16 Lambda - 3) / (24 nu), Lambda = (tau - 1/2)^2, so
@@ -158,6 +159,12 @@ def test_couette_profile_and_wall_stress(tau):
     per_step = wm / avg / nx
     assert per_step[1] == pytest.approx(-stress, rel=1e-9)   # fluid drags the top wall back
     assert per_step[0] == pytest.approx(stress, rel=1e-9)
+    # Pre-collision kinetic stress sum_i f_i c_ix c_iy: the steady linear-shear
+    # populations are f_eq - tau c_iy d_y f_eq (the terms quadratic in u are
+    # even in c_x and drop out), so each site holds -tau rho c_s^2 du/dy and
+    # the lattice sum is that times the total mass.
+    t = oracle.totals(p, g)
+    assert t["pxy_kin"] == pytest.approx(-tau * CS2 * (2 * U / ny) * t["mass"].sum(), rel=1e-12)
 
 
 @pytest.mark.parametrize("tau", [1.116071, 0.8])
@@ -297,6 +304,11 @@ def _poiseuille(H, tau, g=1e-6, rho=(0.3, 0.7), nx=5):
     f, wm = oracle.run(p, f, steps + 200, avg_from=steps)
     u = oracle.fields(p, f)["uphys"]
     assert np.ptp(u[0], axis=1).max() < 1e-15          # no x dependence
+    # the global sums: momentum with the half force (rho = 1) is the profile's
+    # sum, and the bare momentum lacks half the body force on the whole mass
+    t = oracle.totals(p, f)
+    assert t["mom_phys"][0] == pytest.approx(nx * u[0][:, 0].sum(), rel=1e-12)
+    assert t["mom"][0] == pytest.approx(t["mom_phys"][0] - 0.5 * g * t["mass"].sum(), rel=1e-12)
     return u[0][:, 0], u[1], wm / 200 / nx, nu
 
 

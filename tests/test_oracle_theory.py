@@ -159,3 +159,21 @@ def test_flat_surface_tension_integral_of_tanh_profiles():
     one = integrate.quad(integrand, -40 * w, 40 * w, epsabs=1e-14, epsrel=1e-12)[0]
     full = theory.surface_tension_flat(ra, rb, tau, rho0, GA2, GB2, g)
     assert full == pytest.approx(2 * one, rel=1e-4)
+
+
+@pytest.mark.parametrize("G1,gab", [(0.0, 0.6), (-0.63, 0.5785), (-1.2, 0.0)])
+def test_bulk_pressure_is_the_legendre_transform_of_the_free_energy(G1, gab):
+    """P = sum_s rho_s d f / d rho_s - f for the bulk free energy of Sec. IV C
+    without the tau renormalisation (theta -> 1): the ideal terms give
+    c_s^2 rho, the cross term c_s^2 g rho_A rho_B and each self term
+    (G/2) rho I(rho) gives c_s^2 (G/2) psi^2, since (rho I)' = I + psi^2 / rho.
+    So the bulk pressure of Eqs. (12), (14) and the free energy, written
+    independently, must agree."""
+    tau_inf, rho0, h = 1e12, 0.9, 1e-5
+    for ra, rb in [(1.3, 0.4), (0.2, 2.1), (0.9, 0.9)]:
+        f = lambda a, b: theory.bulk_free_energy_tau(a, b, tau_inf, rho0, G1, gab)
+        dfa = (f(ra + h, rb) - f(ra - h, rb)) / (2 * h)
+        dfb = (f(ra, rb + h) - f(ra, rb - h)) / (2 * h)
+        legendre = ra * dfa + rb * dfb - f(ra, rb)
+        P = theory.bulk_pressure(ra, rb, rho0, G1, G1, gab)
+        assert P == pytest.approx(legendre, rel=1e-8, abs=1e-10)
