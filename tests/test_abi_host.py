@@ -159,3 +159,23 @@ def test_probe_library_exports_its_header():
     assert P.hbm_copy(None, None, 4096, 1, 256, 0, 1, None) == -1
     assert P.hbm_copy(16, 32, 100, 1, 256, 0, 1, None) == -1
     assert P.hbm_copy(16, 32, 4096, 1, 256, 0, 3, None) == -1
+
+
+def test_kolmogorov_force_drives_the_requested_mode(L):
+    """lb_kolmogorov_force (host only) returns the body-force amplitude for
+    which the oracle's steady first mode of u_x (Sec. VIII, Eq. (66)) is the
+    requested U0, within the lattice's O(k^2) error at tau = 1.3, ny = 64
+    (0.5%), for both signs of U0; invalid arguments are refused."""
+    import oracle
+    for u0 in (0.01, -0.004):
+        g = ctypes.c_double()
+        assert L.lb_kolmogorov_force(u0, 64, 1.3, ctypes.byref(g)) == lb.LB_OK
+        p = oracle.Params(nx=4, ny=64, tau=(1.3, 1.3), rho0=1.0, Ga=(0, 0), Gr=(0, 0), Gab=0.0,
+                          g_body=g.value)
+        f0 = oracle.init_equilibrium(p, np.full((64, 4), 0.6), np.full((64, 4), 0.4))
+        f, _ = oracle.run(p, f0, 16000)
+        assert oracle.totals(p, f)["u_mode"] == pytest.approx(u0, rel=5e-3)
+    g = ctypes.c_double()
+    for args in ((0.01, 4, 1.0), (0.01, 64, 0.5), (float("nan"), 64, 1.0), (0.01, 64, float("inf"))):
+        assert L.lb_kolmogorov_force(*args, ctypes.byref(g)) == lb.LB_E_INVAL
+    assert L.lb_kolmogorov_force(0.01, 64, 1.0, None) == lb.LB_E_INVAL
