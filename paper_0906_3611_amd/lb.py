@@ -67,6 +67,14 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: the HIP library has not been built "
                           "(run __graft_entry__.build())")
+    # torch ships its own HIP runtime.  Loaded first, it is the one the
+    # library binds to; loaded after the library, a second runtime would sit
+    # in the process, to which torch's device memory and streams (the
+    # workspace and stream handed to lb_create) mean nothing.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp, dp, i64, i32 = ctypes.c_void_p, P(ctypes.c_double), ctypes.c_int64, ctypes.c_int32

@@ -89,3 +89,31 @@ def test_handles_driven_from_separate_threads():
     for k, (_, f_ref) in enumerate(refs):
         assert out[k] is not None, k
         assert np.array_equal(out[k], f_ref), shapes[k]
+
+
+def test_binding_works_without_importing_torch_first(tmp_path):
+    """A program that imports only the binding (torch is pulled in by it
+    before the library loads, so one HIP runtime serves both): a lattice on
+    torch's workspace and stream steps and reports the same mass as the
+    stored initial state."""
+    import os
+    import subprocess
+    import sys
+    prog = r'''
+import json, sys
+sys.path.insert(0, sys.argv[1])
+from paper_0906_3611_amd import lb
+lat = lb.Lattice(70, 45, precision="fp32dev", tau=(1.0, 1.0), rho0=0.83, G_a=(-9.0, -9.0),
+                 G_r=(8.1, 8.1), G_AB=0.405)
+lat.init_noise(5, 0.5, 0.5, 0.01)
+m0 = list(lat.observables()["mass"])
+lat.step(10)
+print(json.dumps({"m0": m0, "m1": list(lat.observables()["mass"])}))
+'''
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", prog, root], capture_output=True, text=True,
+                         timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    import json
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    assert np.allclose(r["m1"], r["m0"], rtol=1e-7)
