@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstdio>
@@ -982,11 +983,17 @@ std::vector<int> seg_signature(const Engine& E, int seg_h) {
 
 }  // namespace
 
-// Candidates: the default shape and forced segment heights 8..256 rows with
+// Candidates: the default shape and forced segment heights 4..256 rows with
 // the current variant, then the six prefetch-depth (0..2) / streaming-store
-// variants at the best height.  Each candidate runs 2 untimed steps (capturing its graph
-// when graphs are on), then `steps` steps timed with HIP events on the
-// engine's stream.  The members' whole device regions (populations, wall
+// variants at the best height.  Each candidate runs 2 untimed steps
+// (capturing its graph when graphs are on), then `steps` steps timed with
+// HIP events on the engine's stream.  The current shape first steps untimed
+// for about 30 ms: after idle or other work the GPU runs a streaming kernel
+// a few per cent slower for its first tens of milliseconds, and a candidate
+// timed in that window would lose to later ones that are no faster.  Every
+// candidate is timed twice, in two passes, and keeps its better time; the
+// default height and the current variant are kept unless another candidate
+// is more than 1% faster.  The members' whole device regions (populations, wall
 // links, reduction slots, flag) are copied aside first and copied back at the
 // end, so the state, the wall-stress averages included, is unchanged.
 namespace {
@@ -1136,31 +1143,69 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   for (int h : {4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
     if (h < ny_max + 8) heights.push_back(h);
   std::vector<std::vector<int>> seen;
-  int best_h = seg0;
-  lbk::StepVariant best_v = E.variant;
-  double best = 1e300;
-  int rc = LB_OK;
+  std::vector<int> hs;  // candidate heights, one per distinct launch; hs[0] = 0, the default
   for (int h : heights) {
     const auto sig = seg_signature(E, h);
     if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
     seen.push_back(sig);
-    double us = 0.0;
-    rc = run(h, best_v, &us);
-    if (rc != LB_OK) break;
-    if (us < best) best = us, best_h = h;
+    hs.push_back(h);
+  }
+  int best_h = seg0;
+  const lbk::StepVariant v0 = E.variant;
+  lbk::StepVariant best_v = v0;
+  double best = 1e300;
+  int rc = LB_OK;
+  {  // settle
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < 16 && rc == LB_OK; ++i) {
+      rc = engine_step(E, steps);
+      if (rc == LB_OK && hipStreamSynchronize(E.stream) != hipSuccess)
+        rc = E.fail(LB_E_DEVICE, "autotune: stream synchronize failed");
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(30)) break;
+    }
+  }
+  // keeps candidate 0 unless another is more than 1% faster
+  auto pick = [](const std::vector<double>& t) {
+    size_t b = 0;
+    for (size_t c = 1; c < t.size(); ++c)
+      if (t[c] < t[b]) b = c;
+    return (b != 0 && !(t[b] < 0.99 * t[0])) ? size_t(0) : b;
+  };
+  if (rc == LB_OK) {
+    std::vector<double> t(hs.size(), 1e300);
+    for (int pass = 0; pass < 2 && rc == LB_OK; ++pass)
+      for (size_t c = 0; c < hs.size() && rc == LB_OK; ++c) {
+        double us = 0.0;
+        rc = run(hs[c], v0, &us);
+        if (rc == LB_OK) t[c] = std::min(t[c], us);
+      }
+    if (rc == LB_OK) {
+      const size_t b = pick(t);
+      best_h = hs[b];
+      best = t[b];
+    }
   }
   if (rc == LB_OK) {
-    const lbk::StepVariant v1 = best_v;
+    std::vector<lbk::StepVariant> vs = {v0};
+    std::vector<double> t = {best};
     const int npf = E.mom ? 1 : 3;  // the moment kernel has no prefetch variants
-    for (int pf = 0; pf < npf && rc == LB_OK; ++pf)
-      for (int nt = 0; nt < 2; ++nt) {
-        const lbk::StepVariant v{pf, nt};
-        if (v.prefetch == v1.prefetch && v.stream_stores == v1.stream_stores) continue;
+    for (int pf = 0; pf < npf; ++pf)
+      for (int nt = 0; nt < 2; ++nt)
+        if (!(pf == v0.prefetch && nt == v0.stream_stores)) {
+          vs.push_back(lbk::StepVariant{pf, nt});
+          t.push_back(1e300);
+        }
+    for (int pass = 0; pass < 2 && rc == LB_OK; ++pass)
+      for (size_t c = 1; c < vs.size() && rc == LB_OK; ++c) {
         double us = 0.0;
-        rc = run(best_h, v, &us);
-        if (rc != LB_OK) break;
-        if (us < best) best = us, best_v = v;
+        rc = run(best_h, vs[c], &us);
+        if (rc == LB_OK) t[c] = std::min(t[c], us);
       }
+    if (rc == LB_OK) {
+      const size_t b = pick(t);
+      best_v = vs[b];
+      best = t[b];
+    }
   }
   // restore the state under the chosen shape (or the original one on error)
   if (rc != LB_OK) best_h = seg0;
