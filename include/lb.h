@@ -261,14 +261,18 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
                   int32_t use_graph);
 
 /* Autotuner: time candidate launch shapes on the lattice's current state and
- * keep the fastest.  Candidates are the default policy and forced segment
+ * keep the fastest.  The current shape first steps untimed for about 30 ms
+ * (a streaming kernel runs slower for its first tens of milliseconds after
+ * idle or copies).  Candidates are the default policy and forced segment
  * heights of 4 to 256 rows with the current code variant, then the six
  * prefetch (0..2) / stream_stores variants at the best height (the moment
  * storage has no prefetch variants: only its two stream_stores variants are
- * timed there); each runs 2 untimed
- * steps and then `steps` (>= 2, rounded up to even) timed with HIP events on
- * the lattice's stream.  Results are kept for the life of the process, by
- * GPU architecture, precision, boundary type, graph use and lattice shapes;
+ * timed there); each runs 2 untimed steps and then `steps` (>= 2, rounded up
+ * to even) timed with HIP events on the lattice's stream, twice (two passes;
+ * the better time counts).  The default height and the current variant are
+ * kept unless another candidate is more than 1% faster.  Results are kept
+ * for the life of the process, by library ABI, GPU architecture, precision,
+ * boundary type, graph use and lattice shapes;
  * steps = 0 applies a kept result without timing anything (and tunes with 16
  * steps when there is none; lb_set_tune_cache keeps results across
  * processes).  The device state (populations, wall links, flags)
