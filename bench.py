@@ -258,24 +258,44 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
                               "points": curve}}
 
 
-def _oracle_job(nx, ny, rho_a, rho_b, steps, out):
+def _oracle_job(nx, ny, rho_a, rho_b, steps, out, twin=False):
+    import numpy as np
     import oracle
     p = oracle.Params(nx=nx, ny=ny, tau=PARAMS["tau"], rho0=PARAMS["rho0"], Ga=PARAMS["G_a"],
                       Gr=PARAMS["G_r"], Gab=PARAMS["G_AB"])
     t0 = time.perf_counter()
-    f, _ = oracle.run(p, oracle.init_equilibrium(p, rho_a, rho_b), steps)
+    f0 = oracle.init_equilibrium(p, rho_a, rho_b)
+    f, _ = oracle.run(p, f0, steps)
     fl = oracle.fields(p, f)
     out.update(rho=fl["rho"], uphys=fl["uphys"], steps=steps, seconds=time.perf_counter() - t0,
                threads=oracle.max_threads())
+    if twin:
+        # the arithmetic-rounding twin: after every step each population is
+        # multiplied by an independent 1 + e, e uniform in [-2^-24, 2^-24)
+        # (rounding at the scale of the populations, as FP32 arithmetic on
+        # them makes it), the envelope the FP32 storage's error is judged by
+        t0 = time.perf_counter()
+        rng = np.random.default_rng(20240)
+        g = f0
+        for t in range(1, steps + 1):
+            g = oracle.step(p, g)
+            g *= 1.0 + 2.0 ** -24 * (2.0 * rng.random(g.shape) - 1.0)
+            if t % 100 == 0:
+                print(f"# oracle twin: {t}/{steps} steps, {time.perf_counter() - t0:.0f} s",
+                      file=sys.stderr, flush=True)
+        tl = oracle.fields(p, g)
+        out.update(twin_rho=tl["rho"], twin_uphys=tl["uphys"], twin_seconds=time.perf_counter() - t0)
 
 
-def start_oracle(nx, ny, rho_a, rho_b, steps):
+def start_oracle(nx, ny, rho_a, rho_b, steps, twin=False):
     """The FP64 oracle on a workload for `steps` steps in a host thread (the
     C library releases the interpreter while it runs), so GPU sections go on
-    meanwhile; join the thread before host-timed sections."""
+    meanwhile; join the thread before host-timed sections.  With twin, the
+    arithmetic-rounding twin follows on the same thread."""
     import threading
     out = {}
-    th = threading.Thread(target=_oracle_job, args=(nx, ny, rho_a, rho_b, steps, out), daemon=True)
+    th = threading.Thread(target=_oracle_job, args=(nx, ny, rho_a, rho_b, steps, out, twin),
+                          daemon=True)
     th.start()
     return th, out
 
@@ -336,6 +356,12 @@ def bench_precision(nx, ny, rho_a, rho_b, oracle_job=None, checkpoints=(1000, 50
                         "u": float(np.abs(u - oj["uphys"]).max())}
         res["vs_oracle"] = {"t": oj["steps"], "oracle_seconds": oj["seconds"],
                             "oracle_threads": oj["threads"], **vs}
+        if "twin_rho" in oj:
+            tw = {"rho": float(np.abs(oj["twin_rho"] - oj["rho"]).max()),
+                  "u": float(np.abs(oj["twin_uphys"] - oj["uphys"]).max())}
+            res["vs_oracle"]["twin_arith"] = tw
+            res["vs_oracle"]["twin_arith_seconds"] = oj["twin_seconds"]
+            res["vs_oracle"]["fp32dev_over_twin_arith"] = {k: vs["fp32dev"][k] / tw[k] for k in tw}
     return res
 
 
@@ -849,6 +875,9 @@ def main():
                     help="skip the FP32-vs-FP64 error study (and its oracle run)")
     ap.add_argument("--precision-oracle-steps", type=int, default=1000,
                     help="steps of the FP64 oracle on the 1024^2 workload (0: none)")
+    ap.add_argument("--precision-twin", action="store_true",
+                    help="also run the oracle's arithmetic-rounding twin (about 5 more minutes "
+                         "of host time at 1000 steps)")
     ap.add_argument("--no-moment", action="store_true", help="skip the tau = 1 moment-storage runs")
     ap.add_argument("--no-ensemble", action="store_true", help="skip the 100-realization ensemble")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched ensemble")
@@ -921,7 +950,8 @@ def main():
     c2a, c2b = inputs.disc_fields(1024, 1024, seed=2, phi=0.7)
     oracle_job = None
     if full and not args.no_precision and args.precision_oracle_steps > 0:
-        oracle_job = start_oracle(1024, 1024, c2a, c2b, args.precision_oracle_steps)
+        oracle_job = start_oracle(1024, 1024, c2a, c2b, args.precision_oracle_steps,
+                                  twin=args.precision_twin)
 
     extra = {}
     r2 = None  # the 1024^2 emulsion, 20000 steps after 200 (the moment storage compares with it)
