@@ -78,3 +78,22 @@ def test_code_hash_ignores_comments_and_whitespace():
     b = "/* the\n same */ int f(int x)\n{\n  return x + 1;  // two\n}\n"
     assert bench.code_hash(a) == bench.code_hash(b)
     assert bench.code_hash(a) != bench.code_hash(a.replace("+ 1", "+ 2"))
+
+
+def test_roofline_record_from_a_timed_run():
+    """achieved = algorithmic bytes per launch / average launch time; frac
+    against the 8 TB/s peak; the copy ceiling beside it."""
+    sites = 4096 * 1024
+    ms = 0.131
+    gbs = 144 * sites / (ms * 1e-3) / 1e9
+    run = {"achieved_gbs": gbs, "mlups": sites / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+           "info": {}, "mass_rel_drift": [0.0, 0.0]}
+    ceiling = {"ceiling_gbs": 6000.0, "best": {"workgroups_per_cu": 2}}
+    r = bench._roofline(run, "fp32dev", sites, True, ceiling)
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["achieved"] == pytest.approx(4610.8, rel=1e-4)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    assert r["frac_of_ceiling"] == pytest.approx(r["achieved"] / 6000.0)
+    assert r["bytes_per_site"] == 144 and r["units_per_launch"] == sites
+    assert r["cache_resident"] is False and "walls" in r["kernel"]
+    assert bench._roofline(run, "fp32dev", 1024 * 1024, False, None)["cache_resident"] is True
