@@ -148,9 +148,22 @@ def cpu_baseline(nx, ny, rho_a, rho_b, walls=False, u_wall=0.0, label="", budget
     oracle.set_threads(1)
     v1, n1, dt1 = _oracle_rate(oracle, p, f, budget_s / 3, 10)
     oracle.set_threads(cores)
+    # the 64^2 parity workload in full (2000 steps), all threads and one
+    from paper_0906_3611_amd import inputs
+    q = oracle.Params(nx=64, ny=64, tau=PARAMS["tau"], rho0=PARAMS["rho0"], Ga=PARAMS["G_a"],
+                      Gr=PARAMS["G_r"], Gab=PARAMS["G_AB"])
+    g0 = oracle.init_equilibrium(q, *inputs.noise_fields(64, 64, 1, 0.5, 0.5, 0.01))
+    c1 = {}
+    for threads in (cores, 1):
+        oracle.set_threads(threads)
+        t0 = time.perf_counter()
+        oracle.run(q, g0, 2000)
+        c1[threads] = 64 * 64 * 2000 / (time.perf_counter() - t0) / 1e6
+    oracle.set_threads(cores)
     return {"value": v, "unit": "MLUPS", "cores": cores, "kind": "oracle",
             "sample": f"{label}, FP64, {n} steps after 1 untimed, {dt:.1f} s",
             "value_1_thread": v1, "sample_1_thread": f"{n1} steps, {dt1:.1f} s",
+            "c1_64x64_2000_steps": {"value": c1[cores], "value_1_thread": c1[1], "unit": "MLUPS"},
             "cpu": _cpu_model(), "nproc": os.cpu_count()}
 
 
@@ -837,6 +850,10 @@ def _roofline(run, precision, sites, walls, ceiling):
            "bytes_per_site": BYTES_PER_SITE[precision], "units_per_launch": sites,
            # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed
            "cache_resident": pop_bytes <= (256 << 20)}
+    if rec["traffic"]:
+        # measured HBM bytes (rocprofv3 counters) over the same launch time
+        rec["traffic_gbs"] = rec["traffic"] / (run["ms_per_step"] * 1e-3) / 1e9
+        rec["traffic_frac"] = rec["traffic_gbs"] / PEAK_HBM_GBS
     if ceiling:
         rec["ceiling_gbs"] = ceiling["ceiling_gbs"]
         rec["frac_of_ceiling"] = run["achieved_gbs"] / ceiling["ceiling_gbs"]
@@ -1043,6 +1060,11 @@ def main():
         line["cpu_baseline"] = cpu_baseline(nx, ny, rho_a, rho_b, walls=c3,
                                             u_wall=HEADLINE_U if c3 else 0.0, label=label)
         line["vs_cpu_baseline"] = main_run["mlups"] / line["cpu_baseline"]["value"]
+        vo = line.get("precision_c2", {}).get("vs_oracle")
+        if vo:  # the oracle run of the precision study, timed there
+            line["cpu_baseline"]["c2_1024x1024_1000_steps"] = {
+                "value": 1024 * 1024 * vo["t"] / vo["oracle_seconds"] / 1e6, "unit": "MLUPS",
+                "cores": vo["oracle_threads"], "note": "ran beside the GPU sections"}
     print(json.dumps(line), flush=True)
 
 
