@@ -271,7 +271,7 @@ def bench_couette(steps=10000, curve_steps=200000, speeds=(0.001, 0.005, 0.02)):
                               "points": curve}}
 
 
-def _oracle_job(nx, ny, rho_a, rho_b, steps, out, twin=False):
+def _cpu_baseline_c2_job(nx, ny, rho_a, rho_b, steps, out, twin=False):
     import numpy as np
     import oracle
     p = oracle.Params(nx=nx, ny=ny, tau=PARAMS["tau"], rho0=PARAMS["rho0"], Ga=PARAMS["G_a"],
@@ -300,15 +300,18 @@ def _oracle_job(nx, ny, rho_a, rho_b, steps, out, twin=False):
         out.update(twin_rho=tl["rho"], twin_uphys=tl["uphys"], twin_seconds=time.perf_counter() - t0)
 
 
-def start_oracle(nx, ny, rho_a, rho_b, steps, twin=False):
-    """The FP64 oracle on a workload for `steps` steps in a host thread (the
-    C library releases the interpreter while it runs), so GPU sections go on
-    meanwhile; join the thread before host-timed sections.  With twin, the
-    arithmetic-rounding twin follows on the same thread."""
+def start_cpu_baseline_c2(nx, ny, rho_a, rho_b, steps, twin=False):
+    """Part of the CPU-baseline leg: the FP64 oracle on the 1024^2 emulsion
+    for `steps` steps in a host thread (the C library releases the
+    interpreter while it runs), so GPU sections go on meanwhile.  Its time is
+    reported with the CPU baseline, and its final fields are what the
+    precision study compares the GPU storages with.  With twin, the
+    arithmetic-rounding twin follows on the same thread.  Join the thread
+    before host-timed sections."""
     import threading
     out = {}
-    th = threading.Thread(target=_oracle_job, args=(nx, ny, rho_a, rho_b, steps, out, twin),
-                          daemon=True)
+    th = threading.Thread(target=_cpu_baseline_c2_job,
+                          args=(nx, ny, rho_a, rho_b, steps, out, twin), daemon=True)
     th.start()
     return th, out
 
@@ -321,8 +324,9 @@ def bench_precision(nx, ny, rho_a, rho_b, oracle_job=None, checkpoints=(1000, 50
     (b) from the initial populations each multiplied by an independent
     1 + e, e uniform in [-2^-24, 2^-24): how far an FP32-level perturbation
     of every site of both species grows by itself in these dynamics.  With
-    oracle_job (start_oracle on the same workload), both GPU storages are
-    also compared with the FP64 oracle at its step count."""
+    oracle_job (the CPU-baseline leg's oracle run on the same workload,
+    start_cpu_baseline_c2), both GPU storages are also compared with the
+    fields of that run at its step count."""
     import numpy as np
     from paper_0906_3611_amd import lb
     runs, masses = {}, {}
@@ -962,13 +966,15 @@ def main():
                        tune_steps=args.tune_steps)
     print(f"# headline {args.precision} {label}: {main_run['mlups']:.0f} MLUPS, "
           f"{main_run['ms_per_step'] * 1e3:.2f} us/step", file=sys.stderr, flush=True)
-    # the oracle on the 1024^2 emulsion runs on the host while the GPU sections go on
+    # the CPU-baseline leg's oracle run on the 1024^2 emulsion goes on on
+    # the host while the GPU sections run
     full = not args.headline_only
     c2a, c2b = inputs.disc_fields(1024, 1024, seed=2, phi=0.7)
     oracle_job = None
-    if full and not args.no_precision and args.precision_oracle_steps > 0:
-        oracle_job = start_oracle(1024, 1024, c2a, c2b, args.precision_oracle_steps,
-                                  twin=args.precision_twin)
+    if (full and not args.no_precision and not args.no_cpu_baseline
+            and args.precision_oracle_steps > 0):
+        oracle_job = start_cpu_baseline_c2(1024, 1024, c2a, c2b, args.precision_oracle_steps,
+                                           twin=args.precision_twin)
 
     extra = {}
     r2 = None  # the 1024^2 emulsion, 20000 steps after 200 (the moment storage compares with it)

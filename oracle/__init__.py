@@ -1,8 +1,11 @@
 """FP64 CPU oracle for the two-species Shan-Chen lattice Boltzmann step.
 
 TEST INFRASTRUCTURE ONLY.  Only the test-suite, ``__graft_entry__.smoke()``
-and the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It is
-the reference the GPU library is checked against and shares no code with it.
+and the ``cpu_baseline`` leg of ``bench.py`` may import this package (that
+leg times the oracle on the benchmark's workloads; the benchmark's precision
+study compares the GPU fields with the fields of the leg's 1024^2 run).  It
+is the reference the GPU library is checked against and shares no code with
+it.
 
 The arithmetic lives in ``lbref.c`` (plain C, FP64, no FMA contraction); this
 module only marshals numpy arrays into it.  ``theory.py`` holds the paper's
