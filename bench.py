@@ -29,6 +29,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+# The CPU baseline's OpenMP threads stay near their data; the OpenMP runtime
+# reads this once, when it first starts (torch starts it on import).
+os.environ.setdefault("OMP_PROC_BIND", "close")
 
 PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
 PAPER_MLUPS = 1024 * 1024 * 1e6 / 86400 / 1e6  # 1024^2, 1e6 steps in about one day (Appendix)
@@ -164,7 +167,8 @@ def cpu_baseline(nx, ny, rho_a, rho_b, walls=False, u_wall=0.0, label="", budget
             "sample": f"{label}, FP64, {n} steps after 1 untimed, {dt:.1f} s",
             "value_1_thread": v1, "sample_1_thread": f"{n1} steps, {dt1:.1f} s",
             "c1_64x64_2000_steps": {"value": c1[cores], "value_1_thread": c1[1], "unit": "MLUPS"},
-            "cpu": _cpu_model(), "nproc": os.cpu_count()}
+            "cpu": _cpu_model(), "nproc": os.cpu_count(),
+            "omp_proc_bind": os.environ.get("OMP_PROC_BIND")}
 
 
 def bench_moment(nx, ny, steps, warmup, rho_a, rho_b, dev_run, r64, no_probe):
