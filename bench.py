@@ -588,39 +588,6 @@ def replay_trace(trace, budget_bytes, tick_s=0.02, schedule="srpt", fill_sites=0
             "budget_bytes": budget_bytes, "pool_ticks": st["ticks"]}
 
 
-def service_times(trace, precision, timed_steps=100):
-    """Per-job service time of a one-job-at-a-time GPU server: measured
-    per-step time of the job's own lattice (plain launches, 10 untimed
-    steps, then timed_steps timed with HIP events) times its step count,
-    plus the measured initialization and result transfer of that lattice."""
-    from paper_0906_3611_amd import lb
-    cache, out = {}, []
-    t_report = time.perf_counter()
-    for k, j in enumerate(trace):
-        if time.perf_counter() - t_report > 30.0:
-            print(f"# {precision} service times: {k}/{len(trace)} jobs", file=sys.stderr, flush=True)
-            t_report = time.perf_counter()
-        key = (j["L"], j["boundary"], j["u_wall"])
-        if key not in cache:
-            kw = _job_spec(j, precision)
-            nx, ny = kw.pop("nx"), kw.pop("ny")
-            t0 = time.perf_counter()
-            lat = lb.Lattice(nx, ny, **kw)
-            lat.init_noise(j["seed"], 0.5, 0.5, 0.01)
-            t_init = time.perf_counter() - t0
-            lat.step(10)
-            ms = _timed(lat.stream, lambda: lat.step(timed_steps))
-            t0 = time.perf_counter()
-            lat.observables()
-            lat.fields()
-            t_fetch = time.perf_counter() - t0
-            lat.close()
-            cache[key] = (ms * 1e-3 / timed_steps, t_init + t_fetch)
-        per_step, fixed = cache[key]
-        out.append(per_step * j["steps"] + fixed)
-    return out
-
-
 def serve_fifo(trace, precision):
     """A sequential server on the same GPU, run for real: jobs in arrival
     order, one at a time, replayed in real time (a job starts once it has
@@ -654,26 +621,16 @@ def serve_fifo(trace, precision):
             "makespan_s": makespan, "value": work / makespan / 1e6, "site_updates": work}
 
 
-def fifo(trace, service):
-    """First-in first-out single server: completion times and latencies."""
-    end, lat = 0.0, []
-    for j, s in zip(trace, service):
-        end = max(end, j["t"]) + s
-        lat.append(end - j["t"])
-    work = sum(j["L"] ** 2 * j["steps"] for j in trace)
-    span = end - trace[0]["t"]
-    return {"latency_s": _percentiles(lat), "makespan_s": span, "value": work / span / 1e6}
-
-
 def bench_serving(n_jobs=100, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5, lockstep=False):
     """Serving trace (Poisson arrivals, half Couette / half periodic, sides
     log-uniform in [64, 2048], steps log-uniform in [1e3, 5e4], FP32 storage)
     replayed in real time against the pool (least-remaining-work schedule;
     with lockstep, again lock-step), then a rate-scaled variant at 0.7 of the
-    capacity measured in the first replay.  Baselines: a sequential
-    first-in first-out server running one job at a time on the same GPU in
-    FP64 storage, run for real on both traces; the same in FP32 storage
-    simulated from per-job service times measured on this GPU."""
+    capacity measured in the first replay.  Baselines, run for real on both
+    traces: sequential first-in first-out servers running one job at a time
+    on the same GPU, in FP32-deviation storage (the pool's own storage and
+    kernels: each job's result is the same bit for bit) and in FP64
+    storage."""
     from paper_0906_3611_amd import inputs
     budget = int(budget_gb * (1 << 30))
     tr = inputs.serving_trace(n_jobs, rate, seed)
@@ -695,7 +652,11 @@ def bench_serving(n_jobs=100, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5, loc
           f"p50 {f64['latency_s']['p50']:.2f} s p99 {f64['latency_s']['p99']:.2f} s",
           file=sys.stderr, flush=True)
     out["fifo_fp64"] = f64
-    out["fifo_fp32dev_simulated"] = fifo(tr, service_times(tr, "fp32dev"))
+    f32 = serve_fifo(tr, "fp32dev")
+    print(f"# same trace, sequential FP32-dev server: {f32['value']:.0f} MLUPS, "
+          f"p50 {f32['latency_s']['p50']:.2f} s p99 {f32['latency_s']['p99']:.2f} s",
+          file=sys.stderr, flush=True)
+    out["fifo_fp32dev"] = f32
     if n_scaled:
         mean_work = sum(j["L"] ** 2 * j["steps"] for j in tr) / len(tr)
         cap_rate = served["value"] * 1e6 / mean_work  # jobs/s at the measured throughput
@@ -703,10 +664,12 @@ def bench_serving(n_jobs=100, rate=50.0, n_scaled=30, budget_gb=8.0, seed=5, loc
         tr2 = inputs.serving_trace(n_scaled, rate2, seed + 1)
         s2 = replay_trace(tr2, budget)
         out["scaled_0p7"] = {"rate": rate2, "jobs": n_scaled, "served": s2,
-                             "fifo_fp64": serve_fifo(tr2, "fp64")}
+                             "fifo_fp64": serve_fifo(tr2, "fp64"),
+                             "fifo_fp32dev": serve_fifo(tr2, "fp32dev")}
         print(f"# scaled trace at {rate2:.2f}/s: p50 {s2['latency_s']['p50']:.2f} s "
               f"p99 {s2['latency_s']['p99']:.2f} s; FIFO FP64 p50 "
-              f"{out['scaled_0p7']['fifo_fp64']['latency_s']['p50']:.2f} s",
+              f"{out['scaled_0p7']['fifo_fp64']['latency_s']['p50']:.2f} s, FIFO FP32-dev p50 "
+              f"{out['scaled_0p7']['fifo_fp32dev']['latency_s']['p50']:.2f} s",
               file=sys.stderr, flush=True)
     return out
 
