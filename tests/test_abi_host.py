@@ -179,3 +179,12 @@ def test_kolmogorov_force_drives_the_requested_mode(L):
     for args in ((0.01, 4, 1.0), (0.01, 64, 0.5), (float("nan"), 64, 1.0), (0.01, 64, float("inf"))):
         assert L.lb_kolmogorov_force(*args, ctypes.byref(g)) == lb.LB_E_INVAL
     assert L.lb_kolmogorov_force(0.01, 64, 1.0, None) == lb.LB_E_INVAL
+
+
+def test_null_handles_are_refused_on_the_host(L):
+    """Every verb on a null handle returns LB_E_INVAL before any device
+    call."""
+    assert L.lb_step(None, 1) == lb.LB_E_INVAL
+    assert L.lb_sync(None) == lb.LB_E_INVAL
+    assert L.lb_batch_step(None, 1) == lb.LB_E_INVAL
+    assert L.lb_pool_advance(None, 1) == lb.LB_E_INVAL

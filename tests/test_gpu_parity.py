@@ -568,3 +568,30 @@ def test_poiseuille_channel_on_gpu(precision, tau):
     # ~4e4 steps: FP64 rounding accumulates to ~1e-12 (measured 6e-13 to 1.2e-12)
     assert np.abs(np.array(o["mass"]) / np.array([ra.sum(), rb.sum()]) - 1).max() < \
         (1e-11 if precision == "fp64" else 1e-7)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev", "fp32mom"])
+def test_step_counts_and_calls_out_of_order(precision):
+    """lb_step(0) enqueues nothing (populations, step count and observables
+    unchanged, bit for bit); a negative count is refused; steps,
+    observables and fields before any initialization are refused without
+    touching the lattice."""
+    lb = _lb()
+    lat = lb.Lattice(20, 12, precision=precision, **C1)
+    for call in (lambda: lat.step(1), lat.observables, lat.fields):
+        with pytest.raises(lb.LBError) as ei:
+            call()
+        assert ei.value.code == lb.LB_E_STATE
+    ra, rb = noise(20, 12, seed=4)
+    lat.init(ra, rb)
+    lat.step(3)
+    before = (lat.populations(), lat.t, lat.observables()["mass"])
+    lat.step(0)
+    after = (lat.populations(), lat.t, lat.observables()["mass"])
+    assert np.array_equal(before[0], after[0]) and before[1] == after[1] == 3
+    assert np.array_equal(before[2], after[2])
+    with pytest.raises(lb.LBError) as ei:
+        lat.step(-1)
+    assert ei.value.code == lb.LB_E_INVAL
+    assert lat.t == 3
+    lat.close()
