@@ -993,7 +993,8 @@ std::vector<int> seg_signature(const Engine& E, int seg_h) {
 // timed in that window would lose to later ones that are no faster.  Every
 // candidate is timed twice, in two passes, and keeps its better time; the
 // default height and the current variant are kept unless another candidate
-// is more than 1% faster.  The members' whole device regions (populations, wall
+// is more than 1% faster.  The chosen shape then steps untimed for about
+// 20 ms before the state is restored.  The members' whole device regions (populations, wall
 // links, reduction slots, flag) are copied aside first and copied back at the
 // end, so the state, the wall-stress averages included, is unchanged.
 namespace {
@@ -1155,15 +1156,18 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
   lbk::StepVariant best_v = v0;
   double best = 1e300;
   int rc = LB_OK;
-  {  // settle
+  // untimed steps of the current shape for about `ms` milliseconds (at most
+  // 16 rounds of `steps` steps)
+  auto hold = [&](int ms) {
     const auto t0 = std::chrono::steady_clock::now();
     for (int i = 0; i < 16 && rc == LB_OK; ++i) {
       rc = engine_step(E, steps);
       if (rc == LB_OK && hipStreamSynchronize(E.stream) != hipSuccess)
         rc = E.fail(LB_E_DEVICE, "autotune: stream synchronize failed");
-      if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(30)) break;
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(ms)) break;
     }
-  }
+  };
+  hold(30);  // settle
   // keeps candidate 0 unless another is more than 1% faster
   auto pick = [](const std::vector<double>& t) {
     size_t b = 0;
@@ -1206,6 +1210,15 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
       best_v = vs[b];
       best = t[b];
     }
+  }
+  // The chosen shape runs last, for about 20 ms, so that steps after the
+  // tuner start from the state that shape runs in rather than from the
+  // last candidate's.
+  if (rc == LB_OK) {
+    E.variant = best_v;
+    E.seg_h = best_h;
+    rc = retile(E);
+    if (rc == LB_OK) hold(20);
   }
   // restore the state under the chosen shape (or the original one on error)
   if (rc != LB_OK) best_h = seg0;
