@@ -270,7 +270,8 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
  * timed there); each runs 2 untimed steps and then `steps` (>= 2, rounded up
  * to even) timed with HIP events on the lattice's stream, twice (two passes;
  * the better time counts).  The default height and the current variant are
- * kept unless another candidate is more than 1% faster.  Results are kept
+ * kept unless another candidate is more than 1% faster, and the chosen shape
+ * steps untimed for about 20 ms before the state is restored.  Results are kept
  * for the life of the process, by library ABI, GPU architecture, precision,
  * boundary type, graph use and lattice shapes;
  * steps = 0 applies a kept result without timing anything (and tunes with 16
