@@ -26,6 +26,7 @@ import os
 import sys
 import time
 
+T_START = time.perf_counter()  # the budget of the whole run counts from here
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -181,8 +182,9 @@ def bench_moment(nx, ny, steps, warmup, rho_a, rho_b, dev_run, r64, no_probe):
            "bytes_per_site": BYTES_PER_SITE["fp32mom"], "achieved_gbs": r["achieved_gbs"],
            "frac": r["achieved_gbs"] / PEAK_HBM_GBS, "launch": r["info"],
            "traffic": traffic_for("fp32mom", nx * ny),
-           "max_abs_rho_vs_fp32dev": float(np.abs(r["rho"] - dev_run["rho"]).max()),
            "mass": list(r["obs"]["mass"])}
+    if dev_run is not None:
+        out["max_abs_rho_vs_fp32dev"] = float(np.abs(r["rho"] - dev_run["rho"]).max())
     if r64 is not None:
         out["max_abs_rho_vs_fp64"] = float(np.abs(r["rho"] - r64["rho"]).max())
     if not no_probe:
@@ -878,11 +880,27 @@ def main():
     ap.add_argument("--serve-lockstep", action="store_true",
                     help="also replay the trace with the lock-step pool schedule")
     ap.add_argument("--serve-budget-gb", type=float, default=8.0)
+    ap.add_argument("--time-budget", type=float, default=480.0,
+                    help="seconds from start after which sections beyond the headline are "
+                         "skipped (each is skipped if its usual duration would overrun; "
+                         "raise it with --precision-twin or a longer serving trace)")
     ap.add_argument("--ingest-counters", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="store HBM traffic per step from rocprofv3 counter CSVs and exit "
                          "(for the --workload and --precision given)")
     args = ap.parse_args()
     c3 = args.workload == "c3"
+    skipped = {}
+
+    def room(name, seconds):
+        """Whether a section that usually takes about `seconds` fits in what
+        is left of --time-budget; if not it is recorded as skipped."""
+        used = time.perf_counter() - T_START
+        if used + seconds <= args.time_budget:
+            print(f"# [{used:.0f} s] {name}", file=sys.stderr, flush=True)
+            return True
+        skipped[name] = f"time budget: {used:.0f} s of {args.time_budget:.0f} s used"
+        print(f"# {name} skipped ({skipped[name]})", file=sys.stderr, flush=True)
+        return False
     nx, ny = {"c3": (4096, 1024), "c2": (1024, 1024), "p4096x1024": (4096, 1024),
               "p4096x4096": (4096, 4096)}[args.workload]
     if args.ingest_counters:
@@ -939,20 +957,21 @@ def main():
     c2a, c2b = inputs.disc_fields(1024, 1024, seed=2, phi=0.7)
     oracle_job = None
     if (full and not args.no_precision and not args.no_cpu_baseline
-            and args.precision_oracle_steps > 0):
+            and args.precision_oracle_steps > 0
+            and args.time_budget - (time.perf_counter() - T_START) > 200):
         oracle_job = start_cpu_baseline_c2(1024, 1024, c2a, c2b, args.precision_oracle_steps,
                                            twin=args.precision_twin)
 
     extra = {}
     r2 = None  # the 1024^2 emulsion, 20000 steps after 200 (the moment storage compares with it)
-    if full:
+    if full and room("c2_1024x1024", 15):
         r2 = run_gpu(1024, 1024, "fp32dev", 20000, 200, c2a, c2b)
         cc = hbm_ceiling(BYTES_PER_SITE["fp32dev"] * 1024 * 1024)
         extra["c2_1024x1024"] = dict(
             _summary(r2, "fp32dev", 1024 * 1024, False, cc),
             workload="1024x1024 periodic disc emulsion phi=0.7 (seed 2), fp32dev, cache-resident")
         print(f"# c2 1024^2: {r2['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
-    if full and not args.no_fp64 and args.precision != "fp64":
+    if full and not args.no_fp64 and args.precision != "fp64" and room("fp64", 20):
         f64 = {}
         for (fx, fy, init, n_steps) in ((1024, 1024, (c2a, c2b), 4000),
                                        (4096, 1024, inputs.noise_fields(4096, 1024, 3, 0.5, 0.5, 0.01),
@@ -963,7 +982,7 @@ def main():
                                  "frac": r["achieved_gbs"] / PEAK_HBM_GBS, "launch": r["info"]}
             print(f"# fp64 {fx}x{fy}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         extra["fp64"] = f64
-    if full and not args.no_probe:
+    if full and not args.no_probe and room("hbm_probe", 30):
         # HBM-resident periodic shapes: 4096 x 1024 (604 MB of FP32 populations)
         # and the graded 4096^2 probe (2.4 GB)
         for (px, py, n_steps) in ((4096, 1024, 2000), (4096, 4096, 400)):
@@ -979,27 +998,31 @@ def main():
         extra["slab_share_4096x134"] = {"value": ps["mlups"], "us_per_step": ps["ms_per_step"] * 1e3,
                                         "owned_rows": 128, "ghost_rows_per_side": 3,
                                         "achieved_gbs": ps["achieved_gbs"]}
-    if full and not args.no_moment and args.precision != "fp32mom":
+    if full and not args.no_moment and args.precision != "fp32mom" and room("moment_tau1", 20):
         extra["moment_tau1"] = bench_moment(1024, 1024, 20000, 200, c2a, c2b, r2, None,
                                             args.no_probe)
         print(f"# fp32mom 1024^2: {extra['moment_tau1']['value']:.0f} MLUPS", file=sys.stderr,
               flush=True)
-    if full and not args.no_couette:
+    if full and not args.no_couette and room("couette", 40):
         extra["couette"] = bench_couette()
-    if full and not args.no_batch:
+    if full and not args.no_batch and room("batched_ensemble", 80):
         extra["batched_ensemble"] = bench_batch(args.ensemble, args.ensemble_steps)
-    if full and not args.no_precision:
-        extra["precision_c2"] = bench_precision(1024, 1024, c2a, c2b, oracle_job)
-        print("# precision study done", file=sys.stderr, flush=True)
-    if full and not args.no_kolmogorov:
-        extra["kolmogorov"] = bench_kolmogorov()
-        print(f"# kolmogorov batch: {extra['kolmogorov']['value']:.0f} MLUPS", file=sys.stderr,
-              flush=True)
-    if full and not args.no_ensemble:
+    # device-bound, so it runs while the host oracle of the precision study
+    # may still be going
+    if full and not args.no_ensemble and room("shear_ensemble", 70):
         extra["shear_ensemble"] = bench_ensemble()
         print(f"# shear ensemble: {extra['shear_ensemble']['value']:.0f} MLUPS", file=sys.stderr,
               flush=True)
-    if full and not args.no_serve:
+    if full and not args.no_precision and room("precision_c2", 20):
+        # the oracle thread is joined here, before the sections timed on the host
+        extra["precision_c2"] = bench_precision(1024, 1024, c2a, c2b, oracle_job)
+        print("# precision study done", file=sys.stderr, flush=True)
+    if full and not args.no_kolmogorov and room("kolmogorov", 30):
+        extra["kolmogorov"] = bench_kolmogorov()
+        print(f"# kolmogorov batch: {extra['kolmogorov']['value']:.0f} MLUPS", file=sys.stderr,
+              flush=True)
+    # the real-time trace with its two sequential servers (FP64, FP32-dev)
+    if full and not args.no_serve and room("serving", 230):
         extra["serving"] = bench_serving(args.serve_jobs, 50.0, args.serve_scaled_jobs,
                                          args.serve_budget_gb, lockstep=args.serve_lockstep)
 
@@ -1029,6 +1052,9 @@ def main():
                           "hardware": "GPU not named", "source": "Appendix"},
     }
     line.update(extra)
+    if skipped:
+        line["skipped_sections"] = skipped
+    line["run_seconds"] = time.perf_counter() - T_START
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(nx, ny, rho_a, rho_b, walls=c3,
                                             u_wall=HEADLINE_U if c3 else 0.0, label=label)

@@ -43,3 +43,22 @@ def test_bench_prints_one_consistent_json_line():
     assert c["kind"] == "oracle" and c["unit"] == "MLUPS" and c["value"] > 0 and c["cores"] >= 1
     assert isinstance(c["sample"], str) and "FP64" in c["sample"]
     assert d["vs_cpu_baseline"] == pytest.approx(d["value"] / c["value"], rel=1e-12)
+
+
+def test_time_budget_skips_the_extra_sections_and_keeps_the_contract():
+    """With no time left after the headline every extra section is recorded
+    as skipped, and the headline, roofline and CPU baseline are still there."""
+    out = subprocess.run([sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "10",
+                          "--warmup", "2", "--tune-steps", "2", "--time-budget", "1"],
+                         capture_output=True, text=True, timeout=280, cwd=ROOT)
+    assert out.returncode == 0, out.stderr[-3000:]
+    lines = [ln for ln in out.stdout.splitlines() if ln.strip()]
+    assert len(lines) == 1, out.stdout[-2000:]
+    d = json.loads(lines[0])
+    assert set(d["skipped_sections"]) == {
+        "c2_1024x1024", "fp64", "hbm_probe", "moment_tau1", "couette", "batched_ensemble",
+        "shear_ensemble", "precision_c2", "kolmogorov", "serving"}
+    for k in d["skipped_sections"]:
+        assert k not in d
+    assert d["value"] > 0 and d["roofline"]["frac"] > 0.2
+    assert d["cpu_baseline"]["value"] > 0 and d["run_seconds"] > 0
