@@ -14,6 +14,8 @@
 #include <mutex>
 #include <sstream>
 
+#include <unistd.h>
+
 namespace lbe {
 static_assert(lbk::kNRed + 2 <= 16, "reduction output rows hold 16 doubles");
 namespace {
@@ -1047,10 +1049,12 @@ void load_tune_file(const std::string& path) {
   }
 }
 
-// Caller holds g_tune_mu.  Writes the whole cache next to the file and
-// renames it into place, so a reader never sees half a file.
+// Caller holds g_tune_mu.  Writes the whole cache next to the file, under
+// a name of this process's own, and renames it into place, so a reader never
+// sees half a file and processes saving at once do not mix their lines (the
+// last rename wins).
 bool save_tune_file(const std::string& path) {
-  const std::string tmp = path + ".tmp";
+  const std::string tmp = path + ".tmp." + std::to_string((long long)getpid());
   {
     std::ofstream out(tmp, std::ios::trunc);
     if (!out) return false;

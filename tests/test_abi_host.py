@@ -134,6 +134,8 @@ def test_tune_cache_file_is_loaded_filtered_and_rewritten(L, tmp_path):
     lines = sorted(path.read_text().splitlines())
     assert lines == ["abi3/gfx950/f32dev/periodic/launch/64x64 8 0 1 12.5",
                      "abi3/gfx950/f32mom/periodic/launch/128x128 4 0 0 9"]
+    # written under a temporary name of this process and renamed into place
+    assert [p.name for p in tmp_path.iterdir()] == ["tune.txt"]
     assert L.lb_set_tune_cache(None) == lb.LB_OK
     assert L.lb_set_tune_cache(str(tmp_path / "missing_dir" / "t.txt").encode()) == lb.LB_E_INVAL
     assert L.lb_set_tune_cache(None) == lb.LB_OK
