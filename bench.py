@@ -1013,7 +1013,7 @@ def main():
         extra["shear_ensemble"] = bench_ensemble()
         print(f"# shear ensemble: {extra['shear_ensemble']['value']:.0f} MLUPS", file=sys.stderr,
               flush=True)
-    if full and not args.no_precision and room("precision_c2", 20):
+    if full and not args.no_precision and room("precision_c2", 220 if args.precision_twin else 20):
         # the oracle thread is joined here, before the sections timed on the host
         extra["precision_c2"] = bench_precision(1024, 1024, c2a, c2b, oracle_job)
         print("# precision study done", file=sys.stderr, flush=True)
@@ -1022,7 +1022,7 @@ def main():
         print(f"# kolmogorov batch: {extra['kolmogorov']['value']:.0f} MLUPS", file=sys.stderr,
               flush=True)
     # the real-time trace with its two sequential servers (FP64, FP32-dev)
-    if full and not args.no_serve and room("serving", 230):
+    if full and not args.no_serve and room("serving", 170 * args.serve_jobs / 100 + 60 * args.serve_scaled_jobs / 30):
         extra["serving"] = bench_serving(args.serve_jobs, 50.0, args.serve_scaled_jobs,
                                          args.serve_budget_gb, lockstep=args.serve_lockstep)
 
