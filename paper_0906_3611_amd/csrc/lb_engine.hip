@@ -807,8 +807,10 @@ int engine_observables(Engine& E, lb_obs* out /*[n]*/) {
   DeviceGuard dg(E.device);
   const int n = (int)E.m.size();
   HIPCK(E, observe_launch(E, launch_args(E, (int)(E.step & 1)), E.stream));
-  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs, n, 0, E.red_out, 16, E.stream));
-  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs, n, 1, E.red_out + lbk::kNRed, 16, E.stream));
+  long long max_slots = 0;
+  for (auto& mm : E.m) max_slots = std::max(max_slots, (long long)mm.d.g.ny * mm.d.g.nstrips);
+  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs, n, 0, E.red_out, 16, max_slots, E.stream));
+  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs, n, 1, E.red_out + lbk::kNRed, 16, 0, E.stream));
   std::vector<double> h((size_t)n * 16);
   HIPCK(E, hipMemcpyAsync(h.data(), E.red_out, h.size() * sizeof(double), hipMemcpyDeviceToHost,
                           E.stream));
@@ -825,8 +827,9 @@ int engine_member_observables(Engine& E, int i, lb_obs* out) {
   DeviceGuard dg(E.device);
   HIPCK(E, observe_launch(E, member_args(E, i), E.stream));
   double* row = E.red_out + (size_t)i * 16;
-  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs + i, 1, 0, row, 16, E.stream));
-  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs + i, 1, 1, row + lbk::kNRed, 16, E.stream));
+  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs + i, 1, 0, row, 16,
+                                       (long long)E.m[i].d.g.ny * E.m[i].d.g.nstrips, E.stream));
+  HIPCK(E, lbk::launch_reduce_lattices(E.d_descs + i, 1, 1, row + lbk::kNRed, 16, 0, E.stream));
   double h[16];
   int flag = 0;
   HIPCK(E, hipMemcpyAsync(h, row, sizeof(h), hipMemcpyDeviceToHost, E.stream));

@@ -110,9 +110,11 @@ hipError_t launch_split_step(const LaunchArgs& a, bool fp64, bool walls, const S
                              hipStream_t st);
 // Fixed-order per-lattice sums of the per-tile slots of each lattice of
 // descs[0..n): its kNRed observe values (which = 0) or its 2 wall
-// accumulators (which = 1), into out[m * out_stride + 0 ..).
+// accumulators (which = 1), into out[m * out_stride + 0 ..).  max_slots:
+// the largest slot count among them (ny * nstrips for which = 0); n at
+// most 65535.  The observe partials are consumed (overwritten in part).
 hipError_t launch_reduce_lattices(const LatticeDesc* descs, int n, int which, double* out,
-                                  int out_stride, hipStream_t st);
+                                  int out_stride, long long max_slots, hipStream_t st);
 // Write the t = 0 state: src buffer in pull layout plus the wall links, from
 // FP64 densities / velocities on the device (u may be null).
 hipError_t launch_init(const Geometry& g, const Coefs& c, bool fp64, bool walls,

@@ -25,6 +25,8 @@
 // (lb_split.hip).
 #include "lb_device.h"
 
+#include <algorithm>
+
 namespace lbk {
 namespace {
 
@@ -421,28 +423,92 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
   }
 }
 
-// Fixed-order reduction of a lattice's partials, one workgroup per lattice:
-// thread t sums slots t, t + 256, ... in order, then a fixed binary tree.
-// Slots are (row, strip) for observables and strips for the wall momentum,
-// so the result depends only on the lattice's size: it is the same bit for
-// bit alone or in a batch, and for any segment height.
-__global__ __launch_bounds__(256) void k_reduce_lattices(const LatticeDesc* __restrict__ descs,
-                                                         int which, double* __restrict__ out,
-                                                         int out_stride) {
-  __shared__ double sh[256];
-  const LatticeDesc* D = descs + blockIdx.x;
-  const long long nslots = which ? (long long)D->g.nstrips : (long long)D->g.ny * D->g.nstrips;
-  const double* __restrict__ in = which ? D->wave_wall : D->wave_red;
-  const int width = which ? 2 : kNRed;
-  for (int m = 0; m < width; ++m) {
-    double v = 0.0;
-    for (long long t = threadIdx.x; t < nslots; t += 256) v += in[t * width + m];
-    sh[threadIdx.x] = v;
+// Fixed-order reduction of a lattice's partials, in two passes.  Slots are
+// (row, strip) for observables (kNRed values each) and strips for the wall
+// momentum (2 values), so the order below depends only on the lattice's
+// size: the result is the same bit for bit alone or in a batch, and for any
+// segment height.
+// Pass 1: workgroup (c, lattice) takes chunk c of kRedChunk slots; thread t
+// sums slots t, t + kRedT, ... of the chunk in order, all WIDTH values of a
+// slot at once (a wave reads contiguous runs), then a fixed binary tree per
+// value.  A lattice of one chunk is done; otherwise the chunk's sums go to
+// the chunk's own first slot, which no other workgroup reads (the observe
+// partials are rewritten by every observe pass).  The wall accumulators
+// carry on across steps, so they are never overwritten: they form one
+// chunk whatever their number.
+// Pass 2: one workgroup per lattice of several chunks sums the chunk sums
+// the same way (thread t: chunks t, t + kRedT, ...; then the tree).
+constexpr int kRedT = 1024;
+constexpr long long kRedChunk = 8LL * kRedT;
+
+__device__ __forceinline__ long long red_slots(const LatticeDesc* D, int width) {
+  return width == kNRed ? (long long)D->g.ny * D->g.nstrips : (long long)D->g.nstrips;
+}
+
+// Sum of v over the workgroup's threads by a fixed tree; the result in sh[0].
+__device__ __forceinline__ void red_tree(double* sh, double v) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = kRedT / 2; h >= 1; h >>= 1) {
+    if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
     __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-      if (threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
-      __syncthreads();
+  }
+}
+
+template <int WIDTH>
+__global__ __launch_bounds__(kRedT) void k_reduce_chunks(const LatticeDesc* __restrict__ descs,
+                                                         double* __restrict__ out, int out_stride) {
+  __shared__ double sh[kRedT];
+  const LatticeDesc* D = descs + blockIdx.y;
+  const long long nslots = red_slots(D, WIDTH);
+  const long long nchunks = WIDTH == kNRed ? (nslots + kRedChunk - 1) / kRedChunk : 1;
+  if (blockIdx.x > 0 && (long long)blockIdx.x >= nchunks) return;  // uniform
+  double* in = WIDTH == kNRed ? D->wave_red : D->wave_wall;
+  const long long lo = (long long)blockIdx.x * kRedChunk;
+  const long long hi = WIDTH == kNRed ? min(nslots, lo + kRedChunk) : nslots;
+  double v[WIDTH];
+#pragma unroll
+  for (int m = 0; m < WIDTH; ++m) v[m] = 0.0;
+#pragma unroll 4
+  for (long long t = lo + threadIdx.x; t < hi; t += kRedT) {
+#pragma unroll
+    for (int m = 0; m < WIDTH; ++m) v[m] += in[t * WIDTH + m];
+  }
+  double r[WIDTH];
+#pragma unroll
+  for (int m = 0; m < WIDTH; ++m) {
+    red_tree(sh, v[m]);  // every read of the chunk precedes its first barrier
+    r[m] = sh[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int m = 0; m < WIDTH; ++m) {
+      if (nchunks <= 1) out[(long long)blockIdx.y * out_stride + m] = r[m];
+      else in[lo * WIDTH + m] = r[m];
     }
+  }
+}
+
+template <int WIDTH>
+__global__ __launch_bounds__(kRedT) void k_reduce_sums(const LatticeDesc* __restrict__ descs,
+                                                       double* __restrict__ out, int out_stride) {
+  __shared__ double sh[kRedT];
+  static_assert(WIDTH == kNRed, "only the observe partials are reduced in two passes");
+  const LatticeDesc* D = descs + blockIdx.x;
+  const long long nchunks = (red_slots(D, WIDTH) + kRedChunk - 1) / kRedChunk;
+  if (nchunks <= 1) return;
+  const double* __restrict__ in = D->wave_red;
+  double v[WIDTH];
+#pragma unroll
+  for (int m = 0; m < WIDTH; ++m) v[m] = 0.0;
+  for (long long c = threadIdx.x; c < nchunks; c += kRedT) {
+#pragma unroll
+    for (int m = 0; m < WIDTH; ++m) v[m] += in[c * kRedChunk * WIDTH + m];
+  }
+#pragma unroll 1
+  for (int m = 0; m < WIDTH; ++m) {
+    red_tree(sh, v[m]);
     if (threadIdx.x == 0) out[(long long)blockIdx.x * out_stride + m] = sh[0];
     __syncthreads();
   }
@@ -580,9 +646,18 @@ hipError_t launch_observe(const LaunchArgs& a, bool fp64, bool walls, hipStream_
 }
 
 hipError_t launch_reduce_lattices(const LatticeDesc* descs, int n, int which, double* out,
-                                  int out_stride, hipStream_t st) {
+                                  int out_stride, long long max_slots, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_lattices, dim3(n), dim3(256), 0, st, descs, which, out, out_stride);
+  const long long chunks = which ? 1 : std::max(1LL, (max_slots + kRedChunk - 1) / kRedChunk);
+  if (n > 65535 || chunks > 0x7fffffffLL) return hipErrorInvalidValue;
+  const dim3 g1((unsigned)chunks, (unsigned)n);
+  if (which)
+    hipLaunchKernelGGL(k_reduce_chunks<2>, g1, dim3(kRedT), 0, st, descs, out, out_stride);
+  else
+    hipLaunchKernelGGL(k_reduce_chunks<kNRed>, g1, dim3(kRedT), 0, st, descs, out, out_stride);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || chunks == 1) return e;
+  hipLaunchKernelGGL(k_reduce_sums<kNRed>, dim3(n), dim3(kRedT), 0, st, descs, out, out_stride);
   return hipGetLastError();
 }
 

@@ -43,6 +43,8 @@ def test_bench_prints_one_consistent_json_line():
     assert c["kind"] == "oracle" and c["unit"] == "MLUPS" and c["value"] > 0 and c["cores"] >= 1
     assert isinstance(c["sample"], str) and "FP64" in c["sample"]
     assert d["vs_cpu_baseline"] == pytest.approx(d["value"] / c["value"], rel=1e-12)
+    # the observables pass, timed on its own
+    assert 0 < d["observables_pass"]["us_per_call"] < 1e5
 
 
 def test_time_budget_skips_the_extra_sections_and_keeps_the_contract():
