@@ -225,6 +225,24 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
   static_for_impl<N>(fn, std::make_integer_sequence<int, N>{});
 }
 
+// Wave sums of the kNRed per-lane observe values of one strip row, each by
+// the same fixed xor tree, taken level by level across all values so that
+// their cross-lane round trips overlap; lane 0 stores them at out[0 ..
+// kNRed) and the values are cleared for the next row.
+__device__ __forceinline__ void wave_sums_store(double (&acc)[kNRed], double* out, int lane) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+    for (int m = 0; m < kNRed; ++m) acc[m] += __shfl_xor(acc[m], off);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int m = 0; m < kNRed; ++m) out[m] = acc[m];
+  }
+#pragma unroll
+  for (int m = 0; m < kNRed; ++m) acc[m] = 0.0;
+}
+
 // Observables of one site at time t, in FP64 (observe launches): fields
 // (rho_s, u', u_phys), optionally the 18 populations, and the partials of
 // mass, momentum, half-force momentum, kinetic P_xy (Sec. III, Eq. (10)),

@@ -396,14 +396,7 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
         // partials of this strip row (fixed lane tree), stored by (row,
         // strip): the totals do not depend on how rows are cut into segments
         const long long rs = ((long long)lattice_row(k - 2) * g.nstrips + strip) * kNRed;
-#pragma unroll
-        for (int m = 0; m < kNRed; ++m) {
-          double v = acc[m];
-#pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-          if (lane == 0) D->wave_red[rs + m] = v;
-          acc[m] = 0.0;
-        }
+        wave_sums_store(acc, D->wave_red + rs, lane);
       }
     });
   }

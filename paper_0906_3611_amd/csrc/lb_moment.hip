@@ -583,14 +583,7 @@ __global__ __launch_bounds__(kWave) void k_mobserve(const LaunchArgs a) {
       }
       if (k >= 4) {
         const long long rs = ((long long)lattice_row(k - 2) * g.nstrips + strip) * kNRed;
-#pragma unroll
-        for (int m = 0; m < kNRed; ++m) {
-          double v = acc[m];
-#pragma unroll
-          for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-          if (lane == 0) D->wave_red[rs + m] = v;
-          acc[m] = 0.0;
-        }
+        wave_sums_store(acc, D->wave_red + rs, lane);
       }
     });
   }
