@@ -265,6 +265,39 @@ def test_observables_do_not_depend_on_segment_height(precision):
     assert oa["pxy_kin"] == ob["pxy_kin"] and oa["avg_count"] == ob["avg_count"] == 13
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_multi_chunk_observables_are_order_fixed(precision):
+    """A lattice whose (row, strip) partials span several reduction chunks
+    (2048 x 600: 19 200 slots, chunks of 8192, the last one partial) gives
+    the same observables bit for bit alone, inside a batch, at another
+    segment height and on a repeated call, and its mass matches the host's
+    FP64 sum of the initial densities to round-off."""
+    lb = _lb()
+    nx, ny = 2048, 600
+    ra, rb = inputs.noise_fields(nx, ny, 9, 0.5, 0.5, 0.05)
+    kw = dict(precision=precision, boundary="couette", u_wall=0.01, **BASE)
+    a, c = lb.Lattice(nx, ny, **kw), lb.Lattice(nx, ny, **kw)
+    small = dict(BASE, nx=67, ny=45, precision=precision, boundary="couette", u_wall=0.01)
+    bat = lb.Batch([dict(BASE, nx=nx, ny=ny, precision=precision, boundary="couette",
+                         u_wall=0.01), small])
+    c.set_launch(seg_h=24)
+    for lat in (a, c):
+        lat.init(ra, rb)
+    bat.init(0, ra, rb)
+    bat.init(1, *_fields_of(small, 7))
+    for run in (a, c, bat):
+        run.step(5)
+    oa, oc, ob = a.observables(), c.observables(), bat.observables()[0]
+    oa2 = a.observables()
+    for o in (oc, ob, oa2):
+        for k in ("mass", "mom", "mom_phys", "wall_stress"):
+            assert np.array_equal(oa[k], o[k]), k
+        assert oa["pxy_kin"] == o["pxy_kin"]
+    mass0 = [float(np.sum(ra)), float(np.sum(rb))]
+    for k in (0, 1):
+        assert abs(oa["mass"][k] / mass0[k] - 1.0) < (1e-12 if precision == "fp64" else 1e-7), k
+
+
 @pytest.mark.parametrize("precision,nx,ny,seg_h", [
     ("fp32dev", 1024, 1024, 8),     # ~2048 tiles: one wave of resident workgroups
     ("fp32dev", 4096, 1024, 32),
