@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define LB_ABI_VERSION 3
+#define LB_ABI_VERSION 4
 
 enum {
   LB_OK = 0,
@@ -234,14 +234,17 @@ int64_t lb_current_step(const lb_lattice* lat);
  * 64 columns (the last may be narrower) and nsegs row segments of about
  * seg_h rows; each (strip, segment) tile is one workgroup of block_threads
  * lanes (128 for FP32 deviation storage, one 64-lane wavefront per species;
- * 64 for the FP64 and moment storages, one wavefront for both species),
- * grid_blocks workgroups per step.  prefetch / stream_stores / use_graph
- * report the code variant in use (1 = on). */
+ * 64 for the FP64 and moment storages, one wavefront for both species), or
+ * tiles_per_group tiles share one, grid_blocks workgroups per step.  prefetch / stream_stores / use_graph
+ * report the code variant in use (1 = on); tiles_per_group the tiles that
+ * share a workgroup in a step launch (1, or 4 where grouping applies: see
+ * lb_set_launch), block_threads and grid_blocks counting them. */
 typedef struct {
   int32_t nstrips, nsegs, ntiles, grid_blocks, block_threads, pitch;
   size_t workspace_bytes;
   size_t population_bytes;   /* one population buffer of every lattice, summed */
   int32_t seg_h, prefetch, stream_stores, use_graph;
+  int32_t tiles_per_group;
 } lb_launch_info;
 int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
 
@@ -256,9 +259,15 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
  *   use_graph: replay lb_step as captured two-step HIP graphs (default 0:
  *     on MI355X under ROCm 7 a replayed step measured 2.3-2.5 us longer than
  *     a plain launch of the same kernel, so graphs only pay where the caller's
- *     host-side launch rate is the limit). */
+ *     host-side launch rate is the limit).
+ *   tiles_per_group: 1 or 4 tiles of adjacent strips per workgroup of the
+ *     FP32 deviation step; 4 applies only to periodic lattices whose strip
+ *     counts (ceil(nx / 64)) are all multiples of 4, elsewhere launches use
+ *     1.  Default 4 where it applies and the population buffers exceed the
+ *     256 MB Infinity Cache (1.3-4.4% faster there; slower on
+ *     cache-resident lattices).  Other values: LB_E_INVAL, nothing changed. */
 int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
-                  int32_t use_graph);
+                  int32_t use_graph, int32_t tiles_per_group);
 
 /* Autotuner: time candidate launch shapes on the lattice's current state and
  * keep the fastest.  The current shape first steps untimed for about 30 ms
@@ -267,7 +276,8 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
  * heights of 4 to 256 rows with the current code variant, then the six
  * prefetch (0..2) / stream_stores variants at the best height (the moment
  * storage has no prefetch variants: only its two stream_stores variants are
- * timed there); each runs 2 untimed steps and then `steps` (>= 2, rounded up
+ * timed there), then, where grouping applies, the other tiles_per_group;
+ * each runs 2 untimed steps and then `steps` (>= 2, rounded up
  * to even) timed with HIP events on the lattice's stream, twice (two passes;
  * the better time counts).  The default height and the current variant are
  * kept unless another candidate is more than 1% faster, and the chosen shape
@@ -339,7 +349,7 @@ int lb_batch_get_launch_info(const lb_batch* b, lb_launch_info* out);
 /* As lb_set_launch; seg_h applies to every lattice of the batch (equal
  * tile heights balance the work of uneven lattices). */
 int lb_batch_set_launch(lb_batch* b, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
-                        int32_t use_graph);
+                        int32_t use_graph, int32_t tiles_per_group);
 /* As lb_autotune, over the whole batch (one common segment height). */
 int lb_batch_autotune(lb_batch* b, int32_t steps, lb_launch_info* out, double* us_per_step);
 void lb_batch_destroy(lb_batch* b);

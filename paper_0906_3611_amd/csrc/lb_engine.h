@@ -56,6 +56,7 @@ struct Engine {
   int64_t step = 0;           // engine step count
   lbk::StepVariant variant{1, 0};
   bool variant_forced = false;  // set by the caller or the autotuner: keep it
+  bool group_ok = false;        // every member allows grouped tiles (set by retile)
   int seg_h = 0;              // forced segment height of every member (0: per-lattice default)
   bool use_graph = false;
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two-step graphs by starting parity
@@ -115,7 +116,8 @@ int engine_reset_averages(Engine& E);
 // reference of its overlap sums (synchronizes).
 int engine_set_reference(Engine& E);
 int engine_sync(Engine& E);
-int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32_t use_graph);
+int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32_t use_graph,
+                       int32_t group);
 int engine_regrid(Engine& E, int seg_h);
 // Time candidate launch shapes on the engine's own state and keep the
 // fastest; the state and step count are restored.  *us_per_step (may be

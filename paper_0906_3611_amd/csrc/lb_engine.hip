@@ -242,6 +242,22 @@ int reserve_shared(Engine& E, int members, int tiles) {
 
 void choose_default_variant(Engine& E);
 
+// Whether the FP32 deviation step may group tiles: periodic, and every
+// (selected) lattice has a whole number of groups of strips, so that the
+// tiles of a group lie in one segment of one lattice.
+bool group_allowed(const Engine& E, const std::vector<int>* sel) {
+  if (!split_kernel(E) || E.walls) return false;
+  auto ok = [&](const Member& mm) { return mm.d.g.nstrips % lbk::kGroupTiles == 0; };
+  if (sel) {
+    for (int i : *sel)
+      if (!ok(E.m[i])) return false;
+  } else {
+    for (auto& mm : E.m)
+      if (!ok(mm)) return false;
+  }
+  return true;
+}
+
 // Member geometries.  A forced height applies to every member.  Otherwise a
 // single lattice uses make_geometry's policy, and several lattices share one
 // segment height: base_seg_h, halved (down to 4) only while the engine's
@@ -306,12 +322,17 @@ void choose_default_variant(Engine& E) {
   // faster with it than without at 1024^2 to 4096^2, periodic and with walls
   // (with walls it costs no occupancy: 124 against 109 VGPRs, four waves per
   // SIMD either way); FP64 (one wave per SIMD) likewise.
+  E.group_ok = group_allowed(E, nullptr);
   if (E.variant_forced) return;
   size_t total_pop = 0;
   for (auto& mm : E.m) total_pop += 2 * mm.pop_bytes;
   const bool hbm = total_pop > kInfinityCacheBytes;
   E.variant.prefetch = (E.mom && hbm) ? 0 : 1;
   E.variant.stream_stores = hbm ? 1 : 0;
+  // Four tiles of adjacent strips per workgroup for periodic lattices larger
+  // than the Infinity Cache (measured 1.3-4.4% faster from 8192 x 512 to
+  // 4096^2; 8% slower on the cache-resident 1024^2 emulsion).
+  E.variant.group = (E.group_ok && hbm) ? lbk::kGroupTiles : 1;
 }
 
 lbk::LaunchArgs launch_args(const Engine& E, int parity) {
@@ -336,16 +357,25 @@ lbk::LaunchArgs member_args(const Engine& E, int i) {
   return a;
 }
 
+// Status of a member's device flag word: bit 0, a non-finite or
+// non-positive density; bit 1, a grouped step launch whose tiles did not
+// march equally far (those tiles were not stepped; the host's grouping rule
+// excludes it).
+int flag_status(Engine& E, int v) {
+  if (v & 2) return E.fail(LB_E_DEVICE, "a grouped step launch met tiles of unequal heights");
+  if (v & 1) return E.fail(LB_E_UNSTABLE, "non-finite or non-positive density on the device");
+  return LB_OK;
+}
+
 int read_flags(Engine& E, std::vector<int>* out) {
   std::vector<int> f(E.m.size(), 0);
   for (size_t i = 0; i < E.m.size(); ++i)
     HIPCK(E, hipMemcpyAsync(&f[i], E.m[i].d.flag, sizeof(int), hipMemcpyDeviceToHost, E.stream));
   HIPCK(E, hipStreamSynchronize(E.stream));
-  bool bad = false;
-  for (int v : f) bad |= (v & 1) != 0;
+  int any = 0;
+  for (int v : f) any |= v;
   if (out) *out = f;
-  if (bad) return E.fail(LB_E_UNSTABLE, "non-finite or non-positive density on the device");
-  return LB_OK;
+  return flag_status(E, any);
 }
 
 // Member i's state is set at engine step E.step: it starts in buf[0].
@@ -405,9 +435,14 @@ int init_from_device_rho(Engine& E, int i, const double* d_rho, const double* d_
 // Capture runs on a private non-blocking stream (the caller's stream may be
 // the null stream, which cannot be captured); replays go to the caller's
 // stream.  The graph holds the two kernel nodes only.
-hipError_t step_launch(const Engine& E, const lbk::LaunchArgs& a, hipStream_t st) {
+hipError_t step_launch(const Engine& E, const lbk::LaunchArgs& a, hipStream_t st,
+                       bool allow_group) {
   if (E.mom) return lbk::launch_moment_step(a, E.variant, st);
-  if (split_kernel(E)) return lbk::launch_split_step(a, E.fp64, E.walls, E.variant, st);
+  if (split_kernel(E)) {
+    lbk::StepVariant v = E.variant;
+    if (!allow_group) v.group = 1;
+    return lbk::launch_split_step(a, E.fp64, E.walls, v, st);
+  }
   return lbk::launch_step(a, E.fp64, E.walls, E.variant, st);
 }
 
@@ -419,7 +454,7 @@ int capture_pair(Engine& E, int parity) {
   if (!E.capture_stream) HIPCK(E, hipStreamCreateWithFlags(&E.capture_stream, hipStreamNonBlocking));
   HIPCK(E, hipStreamBeginCapture(E.capture_stream, hipStreamCaptureModeThreadLocal));
   for (int k = 0; k < 2; ++k) {
-    const hipError_t le = step_launch(E, launch_args(E, (parity + k) & 1), E.capture_stream);
+    const hipError_t le = step_launch(E, launch_args(E, (parity + k) & 1), E.capture_stream, E.group_ok);
     if (le != hipSuccess) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(E.capture_stream, &g);
@@ -714,7 +749,7 @@ int engine_step(Engine& E, int64_t n) {
     }
   }
   for (; k < n; ++k) {
-    HIPCK(E, step_launch(E, launch_args(E, (int)(E.step & 1)), E.stream));
+    HIPCK(E, step_launch(E, launch_args(E, (int)(E.step & 1)), E.stream, E.group_ok));
     ++E.step;
   }
   // every buffer written by a moment step is in pull form; the kernels
@@ -785,9 +820,10 @@ int engine_step_subset(Engine& E, const std::vector<int>& sel, int64_t n) {
   a.ntiles = base;
   a.tiles_per_xcd = (base + 7) / 8;
   a.accumulate_wall = E.walls ? 1 : 0;
+  const bool grp = group_allowed(E, &sel);
   for (int64_t k = 0; k < n; ++k) {
     a.parity = (int)(E.step & 1);
-    HIPCK(E, step_launch(E, a, E.stream));
+    HIPCK(E, step_launch(E, a, E.stream, grp));
     ++E.step;
   }
   for (size_t i = 0; i < E.m.size(); ++i) {
@@ -836,7 +872,7 @@ int engine_member_observables(Engine& E, int i, lb_obs* out) {
   HIPCK(E, hipMemcpyAsync(&flag, E.m[i].d.flag, sizeof(int), hipMemcpyDeviceToHost, E.stream));
   HIPCK(E, hipStreamSynchronize(E.stream));
   fill_obs(E, i, h, flag, out);
-  if (flag & 1) return E.fail(LB_E_UNSTABLE, "non-finite or non-positive density on the device");
+  if (flag & 3) return flag_status(E, flag);
   return LB_OK;
 }
 
@@ -858,7 +894,7 @@ int engine_fields_staged(Engine& E, int i, double* staging, double* rho_a, doubl
   int flag = 0;
   HIPCK(E, hipMemcpyAsync(&flag, E.m[i].d.flag, sizeof(int), hipMemcpyDeviceToHost, E.stream));
   HIPCK(E, hipStreamSynchronize(E.stream));
-  if (flag & 1) return E.fail(LB_E_UNSTABLE, "non-finite or non-positive density on the device");
+  if (flag & 3) return flag_status(E, flag);
   return LB_OK;
 }
 
@@ -953,10 +989,14 @@ int engine_sync(Engine& E) {
   return read_flags(E, nullptr);
 }
 
-int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32_t use_graph) {
+int engine_set_variant(Engine& E, int32_t prefetch, int32_t stream_stores, int32_t use_graph,
+                       int32_t group) {
+  if (group >= 0 && group != 1 && group != lbk::kGroupTiles)
+    return E.fail(LB_E_INVAL, "tiles_per_group must be 1 or 4");
   if (prefetch >= 0) E.variant.prefetch = std::min(prefetch, 2);
   if (stream_stores >= 0) E.variant.stream_stores = stream_stores ? 1 : 0;
-  if (prefetch >= 0 || stream_stores >= 0) E.variant_forced = true;
+  if (group >= 0) E.variant.group = group;
+  if (prefetch >= 0 || stream_stores >= 0 || group >= 0) E.variant_forced = true;
   if (use_graph >= 0) E.use_graph = use_graph != 0;
   drop_graphs(E);
   return LB_OK;
@@ -1007,7 +1047,8 @@ namespace {
 // Autotuner results, by library ABI, GPU architecture, storage, boundary
 // type, graph use and the members' shapes: kept for the life of the
 // process and, after lb_set_tune_cache, in a text file (one result per
-// line: key, segment height, prefetch, streaming stores, us per step).  A
+// line: key, segment height, prefetch, streaming stores, tiles per group,
+// us per step).  A
 // result only selects among launch shapes that give the same numbers bit
 // for bit, so a stale one costs speed, never correctness.
 struct TuneResult {
@@ -1044,9 +1085,9 @@ void load_tune_file(const std::string& path) {
     std::istringstream ls(line);
     std::string key;
     TuneResult r{};
-    if (!(ls >> key >> r.seg_h >> r.v.prefetch >> r.v.stream_stores >> r.us)) continue;
+    if (!(ls >> key >> r.seg_h >> r.v.prefetch >> r.v.stream_stores >> r.v.group >> r.us)) continue;
     if (r.seg_h < 0 || r.v.prefetch < 0 || r.v.prefetch > 2 || (r.v.stream_stores & ~1) ||
-        !(r.us > 0.0))
+        (r.v.group != 1 && r.v.group != lbk::kGroupTiles) || !(r.us > 0.0))
       continue;
     g_tune_cache[key] = r;
   }
@@ -1064,7 +1105,7 @@ bool save_tune_file(const std::string& path) {
     out.precision(17);  // times round-trip
     for (const auto& kv : g_tune_cache)
       out << kv.first << ' ' << kv.second.seg_h << ' ' << kv.second.v.prefetch << ' '
-          << kv.second.v.stream_stores << ' ' << kv.second.us << '\n';
+          << kv.second.v.stream_stores << ' ' << kv.second.v.group << ' ' << kv.second.us << '\n';
     if (!out) return false;
   }
   return std::rename(tmp.c_str(), path.c_str()) == 0;
@@ -1218,6 +1259,21 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
       best = t[b];
     }
   }
+  if (rc == LB_OK && E.group_ok) {
+    // tiles per workgroup at the best height and variant
+    lbk::StepVariant other = best_v;
+    other.group = best_v.group == 1 ? lbk::kGroupTiles : 1;
+    std::vector<double> t = {best, 1e300};
+    for (int pass = 0; pass < 2 && rc == LB_OK; ++pass) {
+      double us = 0.0;
+      rc = run(best_h, other, &us);
+      if (rc == LB_OK) t[1] = std::min(t[1], us);
+    }
+    if (rc == LB_OK && pick(t) == 1) {
+      best_v = other;
+      best = t[1];
+    }
+  }
   // The chosen shape runs last, for about 20 ms, so that steps after the
   // tuner start from the state that shape runs in rather than from the
   // last candidate's.
@@ -1273,9 +1329,11 @@ int set_tune_cache(const char* path) {
 
 void engine_info(const Engine& E, lb_launch_info* out) {
   std::memset(out, 0, sizeof(*out));
+  const int grp = (split_kernel(E) && E.group_ok) ? E.variant.group : 1;
   out->ntiles = E.ntiles;
-  out->grid_blocks = 8 * ((E.ntiles + 7) / 8);
-  out->block_threads = split_kernel(E) ? 2 * lbk::kWave : lbk::kWave;
+  out->grid_blocks = 8 * ((E.ntiles / grp + 7) / 8);
+  out->block_threads = split_kernel(E) ? 2 * lbk::kWave * grp : lbk::kWave;
+  out->tiles_per_group = grp;
   out->workspace_bytes = E.bytes;
   size_t pb = 0;
   for (auto& mm : E.m) pb += mm.pop_bytes;

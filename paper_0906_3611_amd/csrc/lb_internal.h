@@ -96,7 +96,11 @@ struct LaunchArgs {
 struct StepVariant {
   int prefetch;       // rows pulled ahead of the current one (0, 1 or 2)
   int stream_stores;  // nontemporal population stores
+  int group = 1;      // tiles per workgroup of the FP32 deviation step: 1 or kGroupTiles
+                      // (periodic only; every lattice of a grouped launch needs a
+                      // multiple of kGroupTiles strips)
 };
+constexpr int kGroupTiles = 4;
 
 // Launchers (lb_kernels.hip).  All return hipError_t of the launch.
 // launch_step: FP64 steps (FP32 deviation storage steps through

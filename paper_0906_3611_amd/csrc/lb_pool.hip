@@ -88,7 +88,7 @@ int ensure_engine(lb_pool* P, int cls) {
   Engine& E = P->eng[cls];
   const int rc = lbe::engine_create_dynamic(E, (cls & 1) != 0, (cls & 2) != 0, P->stream);
   if (rc != LB_OK) return P->fail(rc, E.err);
-  lbe::engine_set_variant(E, -1, -1, P->use_graph);
+  lbe::engine_set_variant(E, -1, -1, P->use_graph, -1);
   P->eng_ready[cls] = true;
   return LB_OK;
 }
@@ -206,7 +206,7 @@ int lb_pool_set_options(lb_pool* P, int32_t keep_fields, int32_t use_graph) {
   if (use_graph >= 0) {
     P->use_graph = use_graph ? 1 : 0;
     for (int c = 0; c < 4; ++c)
-      if (P->eng_ready[c]) lbe::engine_set_variant(P->eng[c], -1, -1, P->use_graph);
+      if (P->eng_ready[c]) lbe::engine_set_variant(P->eng[c], -1, -1, P->use_graph, -1);
   }
   return LB_OK;
 }

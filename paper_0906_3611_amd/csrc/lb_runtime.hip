@@ -130,10 +130,11 @@ int lb_get_launch_info(const lb_lattice* L, lb_launch_info* out) {
 }
 
 int lb_set_launch(lb_lattice* L, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
-                  int32_t use_graph) {
+                  int32_t use_graph, int32_t tiles_per_group) {
   if (!L) return LB_E_INVAL;
   DeviceGuard dg(L->e.device);
-  lbe::engine_set_variant(L->e, prefetch, stream_stores, use_graph);
+  const int rc = lbe::engine_set_variant(L->e, prefetch, stream_stores, use_graph, tiles_per_group);
+  if (rc != LB_OK) return rc;
   return seg_h >= 0 ? lbe::engine_regrid(L->e, seg_h) : LB_OK;
 }
 
@@ -219,10 +220,11 @@ int lb_batch_get_launch_info(const lb_batch* B, lb_launch_info* out) {
 }
 
 int lb_batch_set_launch(lb_batch* B, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
-                        int32_t use_graph) {
+                        int32_t use_graph, int32_t tiles_per_group) {
   if (!B) return LB_E_INVAL;
   DeviceGuard dg(B->e.device);
-  lbe::engine_set_variant(B->e, prefetch, stream_stores, use_graph);
+  const int rc = lbe::engine_set_variant(B->e, prefetch, stream_stores, use_graph, tiles_per_group);
+  if (rc != LB_OK) return rc;
   return seg_h >= 0 ? lbe::engine_regrid(B->e, seg_h) : LB_OK;
 }
 

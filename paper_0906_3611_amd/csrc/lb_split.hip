@@ -20,11 +20,21 @@
 namespace lbk {
 namespace {
 
-template <typename ST, typename CT, bool DEV, bool WALLS, int PF, bool NT>
-__global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
+// NSUB tiles of adjacent strips of one segment share a workgroup (2 NSUB
+// waves, one barrier per row across all of them): on periodic lattices
+// larger than the Infinity Cache the side loads then hit lines the same CU
+// has just fetched.  Grouped launches need every lattice of the launch to
+// have a multiple of NSUB strips, so that a group's tiles lie in one
+// segment and march equally far.  Each wave checks that once its first
+// loads are in flight; a group that does not satisfy it leaves as a whole,
+// before any barrier, and raises flag bit 2 (reported by the host as a
+// launch error).
+template <typename ST, typename CT, bool DEV, bool WALLS, int PF, bool NT, int NSUB>
+__global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) {
   // Multiply-adds are fused only within one source expression, so every
   // unrolled copy of the march rounds a site alike.
 #pragma clang fp contract(on)
+  static_assert(NSUB == 1 || !WALLS, "grouped tiles are built for periodic lattices only");
   constexpr int W = kWave + 4;     // ring entries per row
   constexpr int NSET = 3 + PF;     // pulled rows held in registers
   constexpr int kItems = 4 * 9;    // ring items of one species: 4 columns x 9 directions
@@ -34,14 +44,22 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   constexpr int kSRing = 6, kJRing = 4;
   // psi and rho of the stencil rows, [species][slot][pos]: species-major so
   // that a wave reading one species hits consecutive banks
-  __shared__ CT ring_p[2][kSRing * W];
-  __shared__ CT ring_r[2][kSRing * W];
-  __shared__ CT rstage[2][kItems];       // pulled ring items of the current row, per species
-  __shared__ CT xj[kJRing][2][2][kWave];  // j_x, j_y of a pulled row, per species
-  __shared__ double wmom[2][2][kWave];   // walls: x momentum to [species][wall] per lane
+  __shared__ CT ring_p_[NSUB][2][kSRing * W];
+  __shared__ CT ring_r_[NSUB][2][kSRing * W];
+  __shared__ CT rstage_[NSUB][2][kItems];       // pulled ring items of the current row, per species
+  __shared__ CT xj_[NSUB][kJRing][2][2][kWave];  // j_x, j_y of a pulled row, per species
+  __shared__ double wmom[2][2][kWave];          // walls: x momentum to [species][wall] per lane
+  const int sub = NSUB > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 7) : 0;
+  auto& ring_p = ring_p_[sub];
+  auto& ring_r = ring_r_[sub];
+  auto& rstage = rstage_[sub];
+  auto& xj = xj_[sub];
   const int b = blockIdx.x;
-  const int tile = (b & 7) * a.tiles_per_xcd + (b >> 3);
-  if (tile >= a.ntiles) return;  // the whole workgroup leaves together
+  const int ngroups = a.ntiles / NSUB;
+  const int gpx = NSUB > 1 ? (ngroups + 7) / 8 : a.tiles_per_xcd;  // groups per XCD
+  const int group = (b & 7) * gpx + (b >> 3);
+  if (group >= ngroups) return;  // the whole workgroup leaves together
+  const int tile = group * NSUB + sub;
   const int li = a.tile_lattice ? a.tile_lattice[tile] : 0;
   const LatticeDesc* __restrict__ D = a.descs + li;
   const Geometry g = D->g;
@@ -49,7 +67,7 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   const int sel = (a.parity ^ D->phase) & 1;
   const int strip = local % g.nstrips;
   const int seg = local / g.nstrips;
-  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // species of this wave
+  const int s = __builtin_amdgcn_readfirstlane((threadIdx.x >> 6) & 1);  // species of this wave
   // (readfirstlane: provably uniform, so per-species values live in scalar registers)
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = g.nx, ny = g.ny;
@@ -178,6 +196,23 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
     constexpr int q = decltype(Q)::value;
     if (q < K) pull_row(q, fr[q], rv[q]);
   });
+  if (NSUB > 1) {
+    // the group's tiles are consecutive: its first and last tile in one
+    // lattice and one segment put all of them there (the same for every wave)
+    const int t0 = group * NSUB, t1 = t0 + NSUB - 1;
+    const int l0 = a.tile_lattice ? a.tile_lattice[t0] : 0;
+    const int l1 = a.tile_lattice ? a.tile_lattice[t1] : 0;
+    bool same = l0 == l1;
+    if (same) {
+      const LatticeDesc* __restrict__ D0 = a.descs + l0;
+      const int base = a.tile_lattice ? D0->tile_base : 0;
+      same = (t0 - base) / D0->g.nstrips == (t1 - base) / D0->g.nstrips;
+    }
+    if (!__builtin_amdgcn_readfirstlane(same)) {
+      if (threadIdx.x == 0) atomicOr(D->flag, 2);
+      return;  // every wave of the group
+    }
+  }
   for (int k0 = 0; k0 < K; k0 += NSET) {
     static_for<NSET>([&](auto J) {
       constexpr int j = decltype(J)::value;
@@ -335,20 +370,25 @@ __global__ __launch_bounds__(2 * kWave) void k_split(const LaunchArgs a) {
   }
 }
 
-template <bool WALLS, int PF, bool NT>
+template <bool WALLS, int PF, bool NT, int NSUB>
 hipError_t launch_split_t(const LaunchArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_split<float, float, true, WALLS, PF, NT>), dim3(8 * a.tiles_per_xcd),
-                     dim3(2 * kWave), 0, st, a);
+  if (a.ntiles % NSUB) return hipErrorInvalidValue;
+  const int gpx = NSUB > 1 ? (a.ntiles / NSUB + 7) / 8 : a.tiles_per_xcd;
+  hipLaunchKernelGGL((k_split<float, float, true, WALLS, PF, NT, NSUB>), dim3(8 * gpx),
+                     dim3(2 * kWave * NSUB), 0, st, a);
   return hipGetLastError();
 }
 
-template <bool WALLS>
+template <bool WALLS, int NSUB>
 hipError_t launch_split_w(const LaunchArgs& a, const StepVariant& v, hipStream_t st) {
   if (v.prefetch >= 2)
-    return v.stream_stores ? launch_split_t<WALLS, 2, true>(a, st) : launch_split_t<WALLS, 2, false>(a, st);
+    return v.stream_stores ? launch_split_t<WALLS, 2, true, NSUB>(a, st)
+                           : launch_split_t<WALLS, 2, false, NSUB>(a, st);
   if (v.prefetch == 1)
-    return v.stream_stores ? launch_split_t<WALLS, 1, true>(a, st) : launch_split_t<WALLS, 1, false>(a, st);
-  return v.stream_stores ? launch_split_t<WALLS, 0, true>(a, st) : launch_split_t<WALLS, 0, false>(a, st);
+    return v.stream_stores ? launch_split_t<WALLS, 1, true, NSUB>(a, st)
+                           : launch_split_t<WALLS, 1, false, NSUB>(a, st);
+  return v.stream_stores ? launch_split_t<WALLS, 0, true, NSUB>(a, st)
+                         : launch_split_t<WALLS, 0, false, NSUB>(a, st);
 }
 
 }  // namespace
@@ -356,7 +396,9 @@ hipError_t launch_split_w(const LaunchArgs& a, const StepVariant& v, hipStream_t
 hipError_t launch_split_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
                              hipStream_t st) {
   if (fp64) return hipErrorInvalidValue;  // FP32 deviation storage only
-  return walls ? launch_split_w<true>(a, v, st) : launch_split_w<false>(a, v, st);
+  if (walls) return v.group > 1 ? hipErrorInvalidValue : launch_split_w<true, 1>(a, v, st);
+  if (v.group == kGroupTiles) return launch_split_w<false, kGroupTiles>(a, v, st);
+  return v.group > 1 ? hipErrorInvalidValue : launch_split_w<false, 1>(a, v, st);
 }
 
 }  // namespace lbk

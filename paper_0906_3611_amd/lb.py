@@ -53,7 +53,7 @@ class lb_launch_info(ctypes.Structure):
                 ("pitch", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
                 ("population_bytes", ctypes.c_size_t), ("seg_h", ctypes.c_int32),
                 ("prefetch", ctypes.c_int32), ("stream_stores", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("tiles_per_group", ctypes.c_int32)]
 
 
 _lib = None
@@ -104,7 +104,7 @@ def load():
         "lb_sync": ([h], ctypes.c_int),
         "lb_current_step": ([h], i64),
         "lb_get_launch_info": ([h, P(lb_launch_info)], ctypes.c_int),
-        "lb_set_launch": ([h, i32, i32, i32, i32], ctypes.c_int),
+        "lb_set_launch": ([h, i32, i32, i32, i32, i32], ctypes.c_int),
         "lb_destroy": ([h], None),
         "lb_batch_workspace_bytes": ([P(lb_params), i32, P(ctypes.c_size_t)], ctypes.c_int),
         "lb_batch_create": ([P(lb_params), i32, vp, ctypes.c_size_t, vp, P(h)], ctypes.c_int),
@@ -120,7 +120,7 @@ def load():
         "lb_batch_sync": ([h], ctypes.c_int),
         "lb_batch_reset_averages": ([h], ctypes.c_int),
         "lb_batch_get_launch_info": ([h, P(lb_launch_info)], ctypes.c_int),
-        "lb_batch_set_launch": ([h, i32, i32, i32, i32], ctypes.c_int),
+        "lb_batch_set_launch": ([h, i32, i32, i32, i32, i32], ctypes.c_int),
         "lb_batch_autotune": ([h, i32, P(lb_launch_info), dp], ctypes.c_int),
         "lb_autotune": ([h, i32, P(lb_launch_info), dp], ctypes.c_int),
         "lb_set_tune_cache": ([ctypes.c_char_p], ctypes.c_int),
@@ -364,10 +364,11 @@ class Lattice(_Handle):
         self._check(self._lib.lb_get_launch_info(self._h, ctypes.byref(li)), "lb_get_launch_info")
         return _info_dict(li)
 
-    def set_launch(self, seg_h=-1, prefetch=-1, stream_stores=-1, use_graph=-1):
+    def set_launch(self, seg_h=-1, prefetch=-1, stream_stores=-1, use_graph=-1,
+                   tiles_per_group=-1):
         """Tuning knobs (lb_set_launch); -1 keeps the current choice."""
         self._check(self._lib.lb_set_launch(self._h, int(seg_h), int(prefetch), int(stream_stores),
-                                            int(use_graph)), "lb_set_launch")
+                                            int(use_graph), int(tiles_per_group)), "lb_set_launch")
 
     def autotune(self, steps=20) -> dict:
         """lb_autotune: keep the fastest launch shape; returns it with its
@@ -466,10 +467,12 @@ class Batch(_Handle):
                     "lb_batch_get_launch_info")
         return _info_dict(li)
 
-    def set_launch(self, seg_h=-1, prefetch=-1, stream_stores=-1, use_graph=-1):
+    def set_launch(self, seg_h=-1, prefetch=-1, stream_stores=-1, use_graph=-1,
+                   tiles_per_group=-1):
         """Tuning knobs (lb_batch_set_launch); seg_h applies to every lattice."""
         self._check(self._lib.lb_batch_set_launch(self._h, int(seg_h), int(prefetch),
-                                                  int(stream_stores), int(use_graph)),
+                                                  int(stream_stores), int(use_graph),
+                                                  int(tiles_per_group)),
                     "lb_batch_set_launch")
 
     def autotune(self, steps=20) -> dict:

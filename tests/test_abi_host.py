@@ -21,7 +21,7 @@ def test_every_declared_function_is_exported(L):
     assert len(names) >= 17
     for n in names:
         assert hasattr(L, n), n
-    assert L.lb_abi_version() == 3
+    assert L.lb_abi_version() == 4
 
 
 def _params(**kw):
@@ -126,14 +126,15 @@ def test_tune_cache_file_is_loaded_filtered_and_rewritten(L, tmp_path):
     """lb_set_tune_cache reads a results file (skipping lines that do not
     parse or hold out-of-range values) and writes the table back whole."""
     path = tmp_path / "tune.txt"
-    path.write_text("abi3/gfx950/f32dev/periodic/launch/64x64 8 0 1 12.5\n"
+    path.write_text("abi4/gfx950/f32dev/periodic/launch/256x256 8 0 1 4 12.5\n"
                     "garbage line\n"
-                    "abi3/gfx950/f64/walls/launch/70x45 16 7 0 30.0\n"   # prefetch out of range
-                    "abi3/gfx950/f32mom/periodic/launch/128x128 4 0 0 9.0\n")
+                    "abi4/gfx950/f64/walls/launch/70x45 16 7 0 1 30.0\n"   # prefetch out of range
+                    "abi4/gfx950/f32dev/periodic/launch/64x64 8 0 1 3 12.5\n"  # tiles per group
+                    "abi4/gfx950/f32mom/periodic/launch/128x128 4 0 0 1 9.0\n")
     assert L.lb_set_tune_cache(str(path).encode()) == lb.LB_OK
     lines = sorted(path.read_text().splitlines())
-    assert lines == ["abi3/gfx950/f32dev/periodic/launch/64x64 8 0 1 12.5",
-                     "abi3/gfx950/f32mom/periodic/launch/128x128 4 0 0 9"]
+    assert lines == ["abi4/gfx950/f32dev/periodic/launch/256x256 8 0 1 4 12.5",
+                     "abi4/gfx950/f32mom/periodic/launch/128x128 4 0 0 1 9"]
     # written under a temporary name of this process and renamed into place
     assert [p.name for p in tmp_path.iterdir()] == ["tune.txt"]
     assert L.lb_set_tune_cache(None) == lb.LB_OK

@@ -129,15 +129,20 @@ def test_launch_variants_do_not_change_fields(precision):
     ref.init(ra, rb)
     ref.step(11)
     f_ref = ref.populations()
-    for seg_h, pf, nt in ((4, 0, 0), (8, 1, 1), (33, 0, 1), (96, 1, 0), (16, 2, 1), (12, 2, 0)):
+    for seg_h, pf, nt, grp in ((4, 0, 0, 1), (8, 1, 1, 1), (33, 0, 1, 4), (96, 1, 0, 4),
+                               (16, 2, 1, 4), (12, 2, 0, 1), (7, 1, 1, 4)):
         lat = lb.Lattice(nx, ny, precision=precision, **BASE)
-        lat.set_launch(seg_h=seg_h, prefetch=pf, stream_stores=nt)
+        lat.set_launch(seg_h=seg_h, prefetch=pf, stream_stores=nt, tiles_per_group=grp)
         info = lat.launch_info()
         assert (info["prefetch"], info["stream_stores"]) == (pf, nt)
-        assert info["block_threads"] == (128 if precision == "fp32dev" else 64)
+        # 200 columns: 4 strips, so four tiles of a segment may share a workgroup
+        g = grp if precision == "fp32dev" else 1
+        assert info["tiles_per_group"] == g
+        assert info["block_threads"] == (128 * g if precision == "fp32dev" else 64)
+        assert info["grid_blocks"] == 8 * ((info["ntiles"] // g + 7) // 8)
         lat.init(ra, rb)
         lat.step(11)
-        assert np.array_equal(lat.populations(), f_ref), (seg_h, pf, nt)
+        assert np.array_equal(lat.populations(), f_ref), (seg_h, pf, nt, grp)
 
 
 @pytest.mark.parametrize("boundary", ["periodic", "couette"])
@@ -298,24 +303,59 @@ def test_multi_chunk_observables_are_order_fixed(precision):
         assert abs(oa["mass"][k] / mass0[k] - 1.0) < (1e-12 if precision == "fp64" else 1e-7), k
 
 
-@pytest.mark.parametrize("precision,nx,ny,seg_h", [
-    ("fp32dev", 1024, 1024, 8),     # ~2048 tiles: one wave of resident workgroups
-    ("fp32dev", 4096, 1024, 32),
-    ("fp32dev", 4096, 4096, 128),   # taller segments keep the halo rows in L2
-    ("fp32dev", 128, 128, 4),       # too small to fill the GPU: shortest march
-    ("fp64", 1024, 1024, 16),       # ~1024 tiles
-    ("fp64", 4096, 4096, 256),
-    ("fp32mom", 4096, 4096, 32),    # issue-bound: at most 32-row segments
-    ("fp32mom", 128, 128, 4),
+@pytest.mark.parametrize("precision,nx,ny,seg_h,grp", [
+    ("fp32dev", 1024, 1024, 8, 1),     # ~2048 tiles: one wave of resident workgroups
+    ("fp32dev", 4096, 1024, 32, 4),    # larger than the Infinity Cache: grouped tiles
+    ("fp32dev", 4096, 4096, 128, 4),   # taller segments keep the halo rows in L2
+    ("fp32dev", 128, 128, 4, 1),       # too small to fill the GPU: shortest march
+    ("fp64", 1024, 1024, 16, 1),       # ~1024 tiles
+    ("fp64", 4096, 4096, 256, 1),
+    ("fp32mom", 4096, 4096, 32, 1),    # issue-bound: at most 32-row segments
+    ("fp32mom", 128, 128, 4, 1),
 ])
-def test_default_tile_policy(precision, nx, ny, seg_h):
+def test_default_tile_policy(precision, nx, ny, seg_h, grp):
     """The default launch shapes are the measured best ones (see the policy
     in lb_engine.hip); a change of the policy shows up here."""
     lat = _lb().Lattice(nx, ny, precision=precision, **BASE)
     info = lat.launch_info()
     assert info["seg_h"] == seg_h, info
+    assert info["tiles_per_group"] == grp, info
     assert info["ntiles"] == info["nstrips"] * info["nsegs"]
     lat.close()
+
+
+def test_grouped_tiles_apply_only_where_every_lattice_allows_them():
+    """Four tiles per workgroup need periodic lattices whose strip counts are
+    all multiples of four; a batch of such lattices steps bit for bit as its
+    members alone, other batches and walled lattices fall back to one tile,
+    and a group size other than 1 or 4 is refused."""
+    lb = _lb()
+    shapes = [(256, 80), (512, 48), (252, 70)]   # 4, 8 and 4 strips
+    specs = [dict(BASE, nx=nx, ny=ny, precision="fp32dev") for nx, ny in shapes]
+    b = lb.Batch(specs)
+    b.set_launch(tiles_per_group=4)
+    assert b.launch_info()["tiles_per_group"] == 4
+    singles = []
+    for i, sp in enumerate(specs):
+        ra, rb = _fields_of(sp, 40 + i)
+        b.init(i, ra, rb)
+        lat = lb.Lattice(sp["nx"], sp["ny"], precision="fp32dev", **BASE)
+        lat.set_launch(tiles_per_group=1)
+        lat.init(ra, rb)
+        lat.step(9)
+        singles.append(lat)
+    b.step(9)
+    for i, lat in enumerate(singles):
+        assert np.array_equal(b.populations(i), lat.populations()), i
+        assert np.array_equal(b.observables()[i]["mass"], lat.observables()["mass"]), i
+    mixed = lb.Batch(specs + [dict(BASE, nx=320, ny=40, precision="fp32dev")])  # 5 strips
+    mixed.set_launch(tiles_per_group=4)
+    assert mixed.launch_info()["tiles_per_group"] == 1
+    walled = lb.Lattice(256, 80, precision="fp32dev", boundary="couette", u_wall=0.01, **BASE)
+    walled.set_launch(tiles_per_group=4)
+    assert walled.launch_info()["tiles_per_group"] == 1
+    with pytest.raises(RuntimeError):
+        walled.set_launch(tiles_per_group=3)
 
 
 def test_autotune_result_persists_across_processes(tmp_path):
