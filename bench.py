@@ -718,7 +718,7 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
     # (name, template arguments, index and value of the argument that selects
     # periodic step launches)
     kname, nargs, at, val = {"fp32mom": ("k_mstep<", 1, None, None),
-                             "fp32dev": ("k_split<", 6, 3, "true" if walls else "false"),  # WALLS
+                             "fp32dev": ("k_split<", 7, 3, "true" if walls else "false"),  # WALLS
                              "fp64": ("k_march<", 7, 4, "0")}[precision]  # MODE
 
     def step(n):

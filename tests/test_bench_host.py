@@ -35,8 +35,8 @@ def test_ingest_counters_scales_by_the_copy(tmp_path, monkeypatch):
     is kept, and only the step kernel of the storage and boundary counts
     (observe launches and other kernels are ignored)."""
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
-    step = "void lbk::(anonymous namespace)::k_split<float, float, true, true, 1, true>(lbk::LaunchArgs)"
-    periodic = "void lbk::(anonymous namespace)::k_split<float, float, true, false, 1, true>(lbk::LaunchArgs)"
+    step = "void lbk::(anonymous namespace)::k_split<float, float, true, true, 1, true, 1>(lbk::LaunchArgs)"
+    periodic = "void lbk::(anonymous namespace)::k_split<float, float, true, false, 1, true, 4>(lbk::LaunchArgs)"
     observe = "void lbk::(anonymous namespace)::k_march<float, double, true, true, 1, 0, false>(lbk::LaunchArgs)"
     copy = "__amd_rocclr_copyBuffer"
     gib_kib = (1 << 30) / 1024
