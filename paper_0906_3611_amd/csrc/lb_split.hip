@@ -21,9 +21,12 @@ namespace lbk {
 namespace {
 
 // NSUB tiles of adjacent strips of one segment share a workgroup (2 NSUB
-// waves, one barrier per row across all of them): on periodic lattices
-// larger than the Infinity Cache the side loads then hit lines the same CU
-// has just fetched.  Grouped launches need every lattice of the launch to
+// waves, one barrier per row across all of them) and one set of LDS ring
+// rows spanning their columns: a tile's ring columns are then its
+// neighbours' own columns, and only the group's first and last tile load
+// ring items (its outer columns); on periodic lattices larger than the
+// Infinity Cache the remaining side loads hit lines the same CU has just
+// fetched.  Grouped launches need every lattice of the launch to
 // have a multiple of NSUB strips, so that a group's tiles lie in one
 // segment and march equally far.  Each wave checks that once its first
 // loads are in flight; a group that does not satisfy it leaves as a whole,
@@ -35,7 +38,7 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
   // unrolled copy of the march rounds a site alike.
 #pragma clang fp contract(on)
   static_assert(NSUB == 1 || !WALLS, "grouped tiles are built for periodic lattices only");
-  constexpr int W = kWave + 4;     // ring entries per row
+  constexpr int W = kWave * NSUB + 4;  // ring entries per row: the group's columns and 2 each side
   constexpr int NSET = 3 + PF;     // pulled rows held in registers
   constexpr int kItems = 4 * 9;    // ring items of one species: 4 columns x 9 directions
   // One barrier per row (after both waves have written it), so a wave can
@@ -44,14 +47,12 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
   constexpr int kSRing = 6, kJRing = 4;
   // psi and rho of the stencil rows, [species][slot][pos]: species-major so
   // that a wave reading one species hits consecutive banks
-  __shared__ CT ring_p_[NSUB][2][kSRing * W];
-  __shared__ CT ring_r_[NSUB][2][kSRing * W];
+  __shared__ CT ring_p[2][kSRing * W];
+  __shared__ CT ring_r[2][kSRing * W];
   __shared__ CT rstage_[NSUB][2][kItems];       // pulled ring items of the current row, per species
   __shared__ CT xj_[NSUB][kJRing][2][2][kWave];  // j_x, j_y of a pulled row, per species
   __shared__ double wmom[2][2][kWave];          // walls: x momentum to [species][wall] per lane
   const int sub = NSUB > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 7) : 0;
-  auto& ring_p = ring_p_[sub];
-  auto& ring_r = ring_r_[sub];
   auto& rstage = rstage_[sub];
   auto& xj = xj_[sub];
   const int b = blockIdx.x;
@@ -83,8 +84,13 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
   const uint32_t ob_c = in_row(col);
   // ring item of this lane (lanes 0..35): column rc of x0 - 2, x0 - 1,
   // x0 + w, x0 + w + 1, direction ri; its source column and in-row offset
-  const bool rl = lane < kItems;
-  const int rc = lane & 3, ri = rl ? lane >> 2 : 0;
+  const int rc = lane & 3;
+  // ring columns are loaded only at the group's outer edges: the left ones by
+  // its first tile, the right ones by its last; the others are the
+  // neighbouring tiles' own columns in the shared ring rows
+  const bool need_l = sub == 0, need_r = sub == NSUB - 1;
+  const bool rl = lane < kItems && (rc < 2 ? need_l : need_r);
+  const int ri = lane < kItems ? lane >> 2 : 0;
   const int rcol = wrap(rc < 2 ? x0 - 2 + rc : x0 + width + (rc - 2), nx);
   const int rsrc = wrap(rcol - cx(ri), nx);
   const int rdy = cy(ri);
@@ -93,7 +99,9 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
   const uint32_t rob =
       (uint32_t)((rsrc >> 6) * (18 * kWave) + (s * 9 + ri) * kWave + (rsrc & 63)) * esz;
   // lanes 0..3 sum the ring column rc = lane; its ring position
-  const int rpos = lane < 2 ? lane : width + lane;
+  const int gpos = kWave * sub;  // this tile's first column in the ring rows, less 2
+  const int rpos = gpos + (lane < 2 ? lane : width + lane);
+  const bool rsum = lane < 4 && (lane < 2 ? need_l : need_r);  // lanes that sum a ring column
   // The own pulls load each direction's run aligned (lane = column, one
   // 256-byte run of the 64-site block) and move the c_x = +-1 directions by
   // one lane in registers: loads shifted by a column straddle two blocks and
@@ -234,10 +242,10 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
       lds_fence();
       const int slot = k % kSRing;
       if (active) {
-        ring_p[s][slot * W + lane + 2] = psi;
-        ring_r[s][slot * W + lane + 2] = rho;
+        ring_p[s][slot * W + gpos + lane + 2] = psi;
+        ring_r[s][slot * W + gpos + lane + 2] = rho;
       }
-      if (lane < 4) {
+      if (rsum) {
         CT acc = rstage[s][lane];
 #pragma unroll
         for (int i = 1; i < 9; ++i) acc += rstage[s][4 * i + lane];
@@ -259,7 +267,7 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
         const CT(&f)[9] = fr[jc];
         int rows[5];
 #pragma unroll
-        for (int d = 0; d < 5; ++d) rows[d] = ((k - 2 + dir * (d - 2)) % kSRing) * W + lane + 2;
+        for (int d = 0; d < 5; ++d) rows[d] = ((k - 2 + dir * (d - 2)) % kSRing) * W + gpos + lane + 2;
         auto psi_at = [&](int dy, int dx, int sp) { return ring_p[sp][rows[dy + 2] + dx]; };
         auto rho_at = [&](int dy, int dx, int sp) { return ring_r[sp][rows[dy + 2] + dx]; };
         const int y = lattice_row(k - 2);
