@@ -261,11 +261,12 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
  *     a plain launch of the same kernel, so graphs only pay where the caller's
  *     host-side launch rate is the limit).
  *   tiles_per_group: 1 or 4 tiles of adjacent strips per workgroup of the
- *     FP32 deviation step; 4 applies only to periodic lattices whose strip
- *     counts (ceil(nx / 64)) are all multiples of 4, elsewhere launches use
- *     1.  Default 4 where it applies and the population buffers exceed the
- *     256 MB Infinity Cache (1.3-4.4% faster there; slower on
- *     cache-resident lattices).  Other values: LB_E_INVAL, nothing changed. */
+ *     FP32 deviation step; 4 applies only where the strip counts
+ *     (ceil(nx / 64)) of all lattices of the launch are multiples of 4,
+ *     elsewhere launches use 1.  Default 4 where it applies and the
+ *     population buffers exceed the 256 MB Infinity Cache (1-5% faster
+ *     there; slower on cache-resident lattices).  Other values: LB_E_INVAL,
+ *     nothing changed. */
 int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stream_stores,
                   int32_t use_graph, int32_t tiles_per_group);
 

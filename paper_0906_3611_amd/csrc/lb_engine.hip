@@ -242,11 +242,11 @@ int reserve_shared(Engine& E, int members, int tiles) {
 
 void choose_default_variant(Engine& E);
 
-// Whether the FP32 deviation step may group tiles: periodic, and every
-// (selected) lattice has a whole number of groups of strips, so that the
-// tiles of a group lie in one segment of one lattice.
+// Whether the FP32 deviation step may group tiles: every (selected)
+// lattice has a whole number of groups of strips, so that the tiles of a
+// group lie in one segment of one lattice.
 bool group_allowed(const Engine& E, const std::vector<int>* sel) {
-  if (!split_kernel(E) || E.walls) return false;
+  if (!split_kernel(E)) return false;
   auto ok = [&](const Member& mm) { return mm.d.g.nstrips % lbk::kGroupTiles == 0; };
   if (sel) {
     for (int i : *sel)
@@ -329,9 +329,10 @@ void choose_default_variant(Engine& E) {
   const bool hbm = total_pop > kInfinityCacheBytes;
   E.variant.prefetch = (E.mom && hbm) ? 0 : 1;
   E.variant.stream_stores = hbm ? 1 : 0;
-  // Four tiles of adjacent strips per workgroup for periodic lattices larger
-  // than the Infinity Cache (measured 1.3-4.4% faster from 8192 x 512 to
-  // 4096^2; 8% slower on the cache-resident 1024^2 emulsion).
+  // Four tiles of adjacent strips per workgroup for lattices larger than the
+  // Infinity Cache (measured 1-5% faster from 8192 x 512 to 4096^2 and on the
+  // 4096 x 1024 channel with walls; 8% slower on the cache-resident 1024^2
+  // emulsion).
   E.variant.group = (E.group_ok && hbm) ? lbk::kGroupTiles : 1;
 }
 

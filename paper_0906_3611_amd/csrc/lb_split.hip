@@ -37,7 +37,6 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
   // Multiply-adds are fused only within one source expression, so every
   // unrolled copy of the march rounds a site alike.
 #pragma clang fp contract(on)
-  static_assert(NSUB == 1 || !WALLS, "grouped tiles are built for periodic lattices only");
   constexpr int W = kWave * NSUB + 4;  // ring entries per row: the group's columns and 2 each side
   constexpr int NSET = 3 + PF;     // pulled rows held in registers
   constexpr int kItems = 4 * 9;    // ring items of one species: 4 columns x 9 directions
@@ -51,10 +50,11 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
   __shared__ CT ring_r[2][kSRing * W];
   __shared__ CT rstage_[NSUB][2][kItems];       // pulled ring items of the current row, per species
   __shared__ CT xj_[NSUB][kJRing][2][2][kWave];  // j_x, j_y of a pulled row, per species
-  __shared__ double wmom[2][2][kWave];          // walls: x momentum to [species][wall] per lane
+  __shared__ double wmom_[NSUB][2][2][kWave];   // walls: x momentum to [species][wall] per lane
   const int sub = NSUB > 1 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 7) : 0;
   auto& rstage = rstage_[sub];
   auto& xj = xj_[sub];
+  auto& wmom = wmom_[sub];
   const int b = blockIdx.x;
   const int ngroups = a.ntiles / NSUB;
   const int gpx = NSUB > 1 ? (ngroups + 7) / 8 : a.tiles_per_xcd;  // groups per XCD
@@ -404,9 +404,10 @@ hipError_t launch_split_w(const LaunchArgs& a, const StepVariant& v, hipStream_t
 hipError_t launch_split_step(const LaunchArgs& a, bool fp64, bool walls, const StepVariant& v,
                              hipStream_t st) {
   if (fp64) return hipErrorInvalidValue;  // FP32 deviation storage only
-  if (walls) return v.group > 1 ? hipErrorInvalidValue : launch_split_w<true, 1>(a, v, st);
-  if (v.group == kGroupTiles) return launch_split_w<false, kGroupTiles>(a, v, st);
-  return v.group > 1 ? hipErrorInvalidValue : launch_split_w<false, 1>(a, v, st);
+  if (v.group == kGroupTiles)
+    return walls ? launch_split_w<true, kGroupTiles>(a, v, st) : launch_split_w<false, kGroupTiles>(a, v, st);
+  if (v.group > 1) return hipErrorInvalidValue;
+  return walls ? launch_split_w<true, 1>(a, v, st) : launch_split_w<false, 1>(a, v, st);
 }
 
 }  // namespace lbk

@@ -306,6 +306,7 @@ def test_multi_chunk_observables_are_order_fixed(precision):
 @pytest.mark.parametrize("precision,nx,ny,seg_h,grp", [
     ("fp32dev", 1024, 1024, 8, 1),     # ~2048 tiles: one wave of resident workgroups
     ("fp32dev", 4096, 1024, 32, 4),    # larger than the Infinity Cache: grouped tiles
+    ("fp32dev-couette", 4096, 1024, 32, 4),
     ("fp32dev", 4096, 4096, 128, 4),   # taller segments keep the halo rows in L2
     ("fp32dev", 128, 128, 4, 1),       # too small to fill the GPU: shortest march
     ("fp64", 1024, 1024, 16, 1),       # ~1024 tiles
@@ -316,7 +317,8 @@ def test_multi_chunk_observables_are_order_fixed(precision):
 def test_default_tile_policy(precision, nx, ny, seg_h, grp):
     """The default launch shapes are the measured best ones (see the policy
     in lb_engine.hip); a change of the policy shows up here."""
-    lat = _lb().Lattice(nx, ny, precision=precision, **BASE)
+    walls = dict(boundary="couette", u_wall=0.005) if precision.endswith("-couette") else {}
+    lat = _lb().Lattice(nx, ny, precision=precision.split("-")[0], **walls, **BASE)
     info = lat.launch_info()
     assert info["seg_h"] == seg_h, info
     assert info["tiles_per_group"] == grp, info
@@ -351,11 +353,34 @@ def test_grouped_tiles_apply_only_where_every_lattice_allows_them():
     mixed = lb.Batch(specs + [dict(BASE, nx=320, ny=40, precision="fp32dev")])  # 5 strips
     mixed.set_launch(tiles_per_group=4)
     assert mixed.launch_info()["tiles_per_group"] == 1
-    walled = lb.Lattice(256, 80, precision="fp32dev", boundary="couette", u_wall=0.01, **BASE)
-    walled.set_launch(tiles_per_group=4)
-    assert walled.launch_info()["tiles_per_group"] == 1
+    fp64 = lb.Lattice(256, 80, precision="fp64", **BASE)
+    fp64.set_launch(tiles_per_group=4)
+    assert fp64.launch_info()["tiles_per_group"] == 1
     with pytest.raises(RuntimeError):
-        walled.set_launch(tiles_per_group=3)
+        fp64.set_launch(tiles_per_group=3)
+
+
+@pytest.mark.parametrize("nx,ny", [(256, 80), (250, 97)])
+def test_grouped_tiles_with_walls_match_single_tiles(nx, ny):
+    """Walls with four tiles per workgroup (each tile with its own wall
+    momentum): populations, observables and the averaged wall stress are
+    those of one tile per workgroup, bit for bit (250 columns: a ragged last
+    strip; 97 rows: segments of unequal heights)."""
+    lb = _lb()
+    ra, rb = inputs.noise_fields(nx, ny, 13, 0.5, 0.5, 0.05)
+    runs = []
+    for g in (1, 4):
+        lat = lb.Lattice(nx, ny, precision="fp32dev", boundary="couette", u_wall=0.01, **BASE)
+        lat.set_launch(seg_h=8, tiles_per_group=g)
+        assert lat.launch_info()["tiles_per_group"] == g
+        lat.init(ra, rb)
+        lat.step(13)
+        runs.append((lat.populations(), lat.observables()))
+    (fa, oa), (fb, ob) = runs
+    assert np.array_equal(fa, fb)
+    for k in ("mass", "mom", "mom_phys", "wall_stress"):
+        assert np.array_equal(oa[k], ob[k]), k
+    assert oa["pxy_kin"] == ob["pxy_kin"]
 
 
 def test_autotune_result_persists_across_processes(tmp_path):
