@@ -182,21 +182,15 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
         f[i] = (CT)((cx(i) > 0 ? lane0 : lane63) ? edge : __builtin_bit_cast(float, moved));
       }
     });
-    if (WALLS) {
-      if (re == 0) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-          f[wall_in_dir(0, j)] = (CT)to_global(wall_in)[((0 * 2 + s) * 3 + j) * nx + col];
-      }
-      if (re == ny - 1) {
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-          f[wall_in_dir(1, j)] = (CT)to_global(wall_in)[((1 * 2 + s) * 3 + j) * nx + col];
-      }
-    }
-    if (WALLS && rl && ((re == 0 && rdy > 0) || (re == ny - 1 && rdy < 0))) {
+    if (WALLS && (re == 0 || re == ny - 1)) {  // a wall row (uniform): links from the wall buffer
       const int wl = re == 0 ? 0 : 1;
-      v = to_global(wall_in)[((wl * 2 + s) * 3 + rj) * nx + rcol];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const CT w = (CT)to_global(wall_in)[((wl * 2 + s) * 3 + j) * nx + col];
+        if (wl) f[wall_in_dir(1, j)] = w;
+        else f[wall_in_dir(0, j)] = w;
+      }
+      if (rl && (wl ? rdy < 0 : rdy > 0)) v = to_global(wall_in)[((wl * 2 + s) * 3 + rj) * nx + rcol];
     }
   };
 
