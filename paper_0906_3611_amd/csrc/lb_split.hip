@@ -247,15 +247,7 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
         ring_r[s][slot * W + rpos] = acc;
       }
       __syncthreads();  // both species' row k is in the ring
-      if (PF && k + PF < K) {
-        // With walls the step is measurably faster (0.7-2.4% from 4096 x 1024
-        // to 4096 x 4096) when a wave issues the next row's loads at raised
-        // priority, ahead of the collisions its SIMD's other waves are in;
-        // periodic lattices gain nothing from it.
-        if (WALLS) __builtin_amdgcn_s_setprio(3);
-        pull_row(k + PF, fr[(j + PF) % NSET], rv[(j + PF) % NSET]);
-        if (WALLS) __builtin_amdgcn_s_setprio(0);
-      }
+      if (PF && k + PF < K) pull_row(k + PF, fr[(j + PF) % NSET], rv[(j + PF) % NSET]);
       if (k >= 4) {
         constexpr int jc = (j + NSET - 2) % NSET;  // set of march row k - 2
         const CT(&f)[9] = fr[jc];
