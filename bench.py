@@ -186,7 +186,7 @@ def bench_moment(nx, ny, steps, warmup, rho_a, rho_b, dev_run, r64, no_probe):
     out = {"value": r["mlups"], "unit": "MLUPS", "ms_per_step": r["ms_per_step"],
            "bytes_per_site": BYTES_PER_SITE["fp32mom"], "achieved_gbs": r["achieved_gbs"],
            "frac": r["achieved_gbs"] / PEAK_HBM_GBS, "launch": r["info"],
-           "traffic": traffic_for("fp32mom", nx * ny),
+           "traffic": traffic_for("fp32mom", nx * ny, info=r["info"]),
            "mass": list(r["obs"]["mass"])}
     if dev_run is not None:
         out["max_abs_rho_vs_fp32dev"] = float(np.abs(r["rho"] - dev_run["rho"]).max())
@@ -685,15 +685,45 @@ def traffic_key(precision, sites, walls=False):
     return f"{precision}{'-couette' if walls else ''}@{sites}"
 
 
-def traffic_for(precision, sites, walls=False):
+# Positions of the launch knobs among the step kernel's template arguments
+# (prefetch depth, streaming stores, tiles per workgroup; None: not a knob of
+# that kernel): k_split<ST, CT, DEV, WALLS, PF, NT, NSUB>,
+# k_march<ST, CT, DEV, WALLS, MODE, PF, NT>, k_mstep<NT>.
+VARIANT_ARGS = {"fp32dev": (4, 5, 6), "fp64": (5, 6, None), "fp32mom": (None, 0, None)}
+
+
+def variant_of_instance(precision, args):
+    """The launch knobs that select a step kernel instance, from its template
+    arguments as rocprofv3 names them."""
+    pf, nt, grp = VARIANT_ARGS[precision]
+    v = {"stream_stores": 1 if args[nt] == "true" else 0}
+    if pf is not None:
+        v["prefetch"] = int(args[pf])
+    v["tiles_per_group"] = int(args[grp]) if grp is not None else 1
+    return v
+
+
+def variant_of_launch(precision, info):
+    """The same knobs from lb_launch_info of the run."""
+    v = {"stream_stores": int(info["stream_stores"]), "tiles_per_group": int(info.get("tiles_per_group", 1))}
+    if VARIANT_ARGS[precision][0] is not None:
+        v["prefetch"] = int(info["prefetch"])
+    return v
+
+
+def traffic_for(precision, sites, walls=False, info=None):
     """HBM bytes per step launch measured with rocprofv3 counters (scaled by
-    a plain copy of known size), if they were taken on the current kernel."""
+    a plain copy of known size), if they were taken on the current kernel
+    sources and on the kernel instance the run launches (info: its
+    lb_launch_info)."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         rec = json.load(fh)
     ent = rec.get(traffic_key(precision, sites, walls))
     if not ent or ent.get("kernel_sha256_16") != kernel_hash(precision):
+        return None
+    if info is not None and ent.get("variant") != variant_of_launch(precision, info):
         return None
     return ent["bytes_per_launch"]
 
@@ -721,11 +751,19 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
                              "fp32dev": ("k_split<", 7, 3, "true" if walls else "false"),  # WALLS
                              "fp64": ("k_march<", 7, 4, "0")}[precision]  # MODE
 
+    def targs(n):
+        return n.split(kname, 1)[1].split(">", 1)[0].split(", ")
+
     def step(n):
         if kname not in n:
             return False
-        args = n.split(kname, 1)[1].split(">", 1)[0].split(", ")
+        args = targs(n)
         return len(args) == nargs and (at is None or args[at] == val)
+    # the run must have launched one instance of the step kernel
+    names = {r["Kernel_Name"] for r in csv.DictReader(open(fetch_csv)) if step(r["Kernel_Name"])}
+    if len(names) != 1:
+        raise SystemExit(f"{len(names)} step kernel instances in {fetch_csv} (one expected)")
+    variant = variant_of_instance(precision, targs(names.pop()))
     copy = lambda n: "copyBuffer" in n
     kib = copy_bytes / 1024
     f_scale = kib / per_dispatch(copy_fetch_csv, copy)
@@ -737,7 +775,7 @@ def ingest_counters(precision, sites, fetch_csv, write_csv, copy_fetch_csv, copy
         rec = json.load(open(TRAFFIC_FILE))
     rec.pop("kernel_sha256_16", None)  # older single-hash format
     key = traffic_key(precision, sites, walls)
-    rec[key] = {"kernel_sha256_16": kernel_hash(precision),
+    rec[key] = {"kernel_sha256_16": kernel_hash(precision), "variant": variant,
                       "sites": sites, "bytes_per_launch": fetch + write, "fetch_bytes": fetch,
                       "write_bytes": write, "fetch_scale": f_scale, "write_scale": w_scale,
                       "algorithmic_bytes": BYTES_PER_SITE[precision] * sites}
@@ -823,7 +861,7 @@ def _roofline(run, precision, sites, walls, ceiling):
     pop_bytes = BYTES_PER_SITE[precision] * sites  # both population buffers (half each)
     rec = {"bound": "hbm", "achieved": run["achieved_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
            "frac": run["achieved_gbs"] / PEAK_HBM_GBS,
-           "traffic": traffic_for(precision, sites, walls),
+           "traffic": traffic_for(precision, sites, walls, run.get("info")),
            "kernel": STEP_KERNEL[precision] + (" (walls)" if walls else ""),
            "bytes_per_site": BYTES_PER_SITE[precision], "units_per_launch": sites,
            # both buffers fit in the 256 MB Infinity Cache: reads can be served above HBM speed

@@ -255,6 +255,8 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
  *     averages carry on.
  *   prefetch: rows whose loads are in flight ahead of the current one
  *     (0, 1 or 2; larger values mean 2; the moment storage ignores it).
+ *     Default 1, and 0 where tiles are grouped or the moment storage
+ *     exceeds the Infinity Cache.
  *   stream_stores: nontemporal population stores.
  *   use_graph: replay lb_step as captured two-step HIP graphs (default 0:
  *     on MI355X under ROCm 7 a replayed step measured 2.3-2.5 us longer than
@@ -275,7 +277,8 @@ int lb_set_launch(lb_lattice* lat, int32_t seg_h, int32_t prefetch, int32_t stre
  * (a streaming kernel runs slower for its first tens of milliseconds after
  * idle or copies).  Candidates are the default policy and forced segment
  * heights of 4 to 256 rows with the current code variant, then the six
- * prefetch (0..2) / stream_stores variants at the best height (the moment
+ * prefetch (0..2) / stream_stores variants at the best height, each with
+ * the current tiles_per_group (the moment
  * storage has no prefetch variants: only its two stream_stores variants are
  * timed there), then, where grouping applies, the other tiles_per_group;
  * each runs 2 untimed steps and then `steps` (>= 2, rounded up

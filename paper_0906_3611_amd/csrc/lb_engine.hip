@@ -318,22 +318,25 @@ int retile(Engine& E) {
 void choose_default_variant(Engine& E) {
   // Defaults (measured): streaming stores when the population buffers
   // exceed the 256 MB Infinity Cache.  A one-row prefetch for the
-  // population storages: FP32 deviations (one wave per species) step 1.6-3.7%
-  // faster with it than without at 1024^2 to 4096^2, periodic and with walls
-  // (with walls it costs no occupancy: 124 against 109 VGPRs, four waves per
-  // SIMD either way); FP64 (one wave per SIMD) likewise.
+  // population storages with one tile per workgroup: FP32 deviations (one
+  // wave per species) step 1.6-3.7% faster with it than without at 1024^2 to
+  // 4096^2, periodic and with walls; FP64 (one wave per SIMD) likewise.
+  // Grouped tiles step 1.5-4% faster without it (2048^2 to 8192 x 1024,
+  // periodic and with walls; 1024 x 4096 and 2048 x 1024 the same): the
+  // group's eight waves meet at every row's barrier, and loads issued
+  // there, all waves at once, gain nothing from being issued a row early.
   E.group_ok = group_allowed(E, nullptr);
   if (E.variant_forced) return;
   size_t total_pop = 0;
   for (auto& mm : E.m) total_pop += 2 * mm.pop_bytes;
   const bool hbm = total_pop > kInfinityCacheBytes;
-  E.variant.prefetch = (E.mom && hbm) ? 0 : 1;
   E.variant.stream_stores = hbm ? 1 : 0;
   // Four tiles of adjacent strips per workgroup for lattices larger than the
   // Infinity Cache (measured 1-5% faster from 8192 x 512 to 4096^2 and on the
   // 4096 x 1024 channel with walls; 8% slower on the cache-resident 1024^2
   // emulsion).
   E.variant.group = (E.group_ok && hbm) ? lbk::kGroupTiles : 1;
+  E.variant.prefetch = (hbm && (E.mom || E.variant.group > 1)) ? 0 : 1;
 }
 
 lbk::LaunchArgs launch_args(const Engine& E, int parity) {
@@ -1245,7 +1248,7 @@ int engine_autotune(Engine& E, int steps, double* us_per_step) {
     for (int pf = 0; pf < npf; ++pf)
       for (int nt = 0; nt < 2; ++nt)
         if (!(pf == v0.prefetch && nt == v0.stream_stores)) {
-          vs.push_back(lbk::StepVariant{pf, nt});
+          vs.push_back(lbk::StepVariant{pf, nt, v0.group});
           t.push_back(1e300);
         }
     for (int pass = 0; pass < 2 && rc == LB_OK; ++pass)

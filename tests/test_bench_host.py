@@ -55,9 +55,42 @@ def test_ingest_counters_scales_by_the_copy(tmp_path, monkeypatch):
     assert rec["bytes_per_launch"] == pytest.approx(rec["fetch_bytes"] + rec["write_bytes"])
     assert rec["algorithmic_bytes"] == 144 * sites
     assert rec["kernel_sha256_16"] == bench.kernel_hash("fp32dev")
-    # the benchmark reports it for that kernel and boundary only
+    # the kernel instance it was taken on: prefetch 1, streaming stores, one tile per workgroup
+    assert rec["variant"] == {"prefetch": 1, "stream_stores": 1, "tiles_per_group": 1}
+    # the benchmark reports it for that kernel, boundary and instance only
     assert bench.traffic_for("fp32dev", sites, walls=True) == pytest.approx(rec["bytes_per_launch"])
     assert bench.traffic_for("fp32dev", sites, walls=False) is None
+    same = {"prefetch": 1, "stream_stores": 1, "tiles_per_group": 1, "seg_h": 32}
+    assert bench.traffic_for("fp32dev", sites, True, same) == pytest.approx(rec["bytes_per_launch"])
+    for knob, other in (("prefetch", 0), ("stream_stores", 0), ("tiles_per_group", 4)):
+        assert bench.traffic_for("fp32dev", sites, True, dict(same, **{knob: other})) is None, knob
+
+
+def test_ingest_counters_needs_one_step_kernel_instance(tmp_path, monkeypatch):
+    """Counters of a run that launched two instances of the step kernel (an
+    autotuner inside the profiled command) cannot be attributed to one."""
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "traffic.json"))
+    a = "void lbk::(anonymous namespace)::k_split<float, float, true, false, 1, true, 4>(lbk::LaunchArgs)"
+    b = "void lbk::(anonymous namespace)::k_split<float, float, true, false, 0, true, 4>(lbk::LaunchArgs)"
+    copy = "__amd_rocclr_copyBuffer"
+    _dump(tmp_path / "f.csv", [(a, 1.0), (b, 1.0)])
+    _dump(tmp_path / "w.csv", [(a, 1.0), (b, 1.0)])
+    _dump(tmp_path / "c.csv", [(copy, 1.0)])
+    with pytest.raises(SystemExit, match="instances"):
+        bench.ingest_counters("fp32dev", 4096 * 1024, str(tmp_path / "f.csv"), str(tmp_path / "w.csv"),
+                              str(tmp_path / "c.csv"), str(tmp_path / "c.csv"))
+
+
+def test_launch_knobs_read_from_kernel_names():
+    """The template arguments that carry prefetch, streaming stores and tiles
+    per workgroup, for each storage's step kernel."""
+    assert bench.variant_of_instance("fp32dev", "float, float, true, true, 0, true, 4".split(", ")) == \
+        {"prefetch": 0, "stream_stores": 1, "tiles_per_group": 4}
+    assert bench.variant_of_instance("fp64", "double, double, false, false, 0, 2, false".split(", ")) == \
+        {"prefetch": 2, "stream_stores": 0, "tiles_per_group": 1}
+    assert bench.variant_of_instance("fp32mom", ["true"]) == {"stream_stores": 1, "tiles_per_group": 1}
+    assert bench.variant_of_launch("fp32mom", {"prefetch": 0, "stream_stores": 1, "tiles_per_group": 1}) == \
+        {"stream_stores": 1, "tiles_per_group": 1}
 
 
 def test_committed_traffic_records_are_current_and_plausible():
@@ -71,6 +104,12 @@ def test_committed_traffic_records_are_current_and_plausible():
     assert "fp32dev-couette@4194304" in current
     for k, v in current.items():
         assert 1.0 <= v["bytes_per_launch"] / v["algorithmic_bytes"] <= 1.2, k
+        # each names the kernel instance it was taken on
+        assert set(v["variant"]) >= {"stream_stores", "tiles_per_group"}, k
+    # the HBM-resident FP32-deviation records are of the default launch there:
+    # four tiles per workgroup, no prefetch, streaming stores
+    for k in ("fp32dev-couette@4194304", "fp32dev@4194304", "fp32dev@16777216"):
+        assert current[k]["variant"] == {"prefetch": 0, "stream_stores": 1, "tiles_per_group": 4}, k
 
 
 def test_code_hash_ignores_comments_and_whitespace():
@@ -87,7 +126,7 @@ def test_roofline_record_from_a_timed_run():
     ms = 0.131
     gbs = 144 * sites / (ms * 1e-3) / 1e9
     run = {"achieved_gbs": gbs, "mlups": sites / (ms * 1e-3) / 1e6, "ms_per_step": ms,
-           "info": {}, "mass_rel_drift": [0.0, 0.0]}
+           "info": {"prefetch": 0, "stream_stores": 1, "tiles_per_group": 4}, "mass_rel_drift": [0.0, 0.0]}
     ceiling = {"ceiling_gbs": 6000.0, "best": {"workgroups_per_cu": 2}}
     r = bench._roofline(run, "fp32dev", sites, True, ceiling)
     assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
