@@ -303,7 +303,12 @@ __global__ __launch_bounds__(kWave) void k_march(const LaunchArgs a) {
   const int width = min(kWave, nx - x0);
   const int y0 = (int)((long long)seg * ny / g.nsegs);
   const int y1 = (int)((long long)(seg + 1) * ny / g.nsegs);
-  const int dir = (seg & 1) ? -1 : 1;
+  // Adjacent segments march towards each other, and every segment turns
+  // round at each step (sel alternates), so a step first reads the rows the
+  // previous step wrote last: with buffers a little larger than the 256 MB
+  // Infinity Cache those are still there (with plain stores).  Each site's
+  // arithmetic does not depend on the direction.
+  const int dir = ((seg ^ sel) & 1) ? -1 : 1;
   const bool active = lane < width;
   // interior column (inactive lanes read a valid duplicate column)
   const int col = active ? x0 + lane : wrap(x0 + lane, nx);

@@ -303,18 +303,19 @@ def test_multi_chunk_observables_are_order_fixed(precision):
         assert abs(oa["mass"][k] / mass0[k] - 1.0) < (1e-12 if precision == "fp64" else 1e-7), k
 
 
-@pytest.mark.parametrize("precision,nx,ny,seg_h,grp,pf", [
-    ("fp32dev", 1024, 1024, 8, 1, 1),     # ~2048 tiles: one wave of resident workgroups
-    ("fp32dev", 4096, 1024, 32, 4, 0),    # larger than the Infinity Cache: grouped tiles
-    ("fp32dev-couette", 4096, 1024, 32, 4, 0),
-    ("fp32dev", 4096, 4096, 128, 4, 0),   # taller segments keep the halo rows in L2
-    ("fp32dev", 128, 128, 4, 1, 1),       # too small to fill the GPU: shortest march
-    ("fp64", 1024, 1024, 16, 1, 1),       # ~1024 tiles
-    ("fp64", 4096, 4096, 256, 1, 1),
-    ("fp32mom", 4096, 4096, 32, 1, 0),    # issue-bound: at most 32-row segments
-    ("fp32mom", 128, 128, 4, 1, 1),
+@pytest.mark.parametrize("precision,nx,ny,seg_h,grp,pf,nt", [
+    ("fp32dev", 1024, 1024, 8, 1, 1, 0),     # ~2048 tiles: one wave of resident workgroups
+    ("fp32dev", 4096, 1024, 32, 4, 0, 1),    # larger than the Infinity Cache: grouped tiles
+    ("fp32dev-couette", 4096, 1024, 32, 4, 0, 1),
+    ("fp32dev", 4096, 4096, 128, 4, 0, 1),   # taller segments keep the halo rows in L2
+    ("fp32dev", 128, 128, 4, 1, 1, 0),       # too small to fill the GPU: shortest march
+    ("fp64", 1024, 1024, 16, 1, 1, 0),       # ~1024 tiles; under twice the Infinity Cache
+    ("fp64", 4096, 1024, 64, 1, 1, 1),
+    ("fp64", 4096, 4096, 256, 1, 1, 1),
+    ("fp32mom", 4096, 4096, 32, 1, 0, 1),    # issue-bound: at most 32-row segments
+    ("fp32mom", 128, 128, 4, 1, 1, 0),
 ])
-def test_default_tile_policy(precision, nx, ny, seg_h, grp, pf):
+def test_default_tile_policy(precision, nx, ny, seg_h, grp, pf, nt):
     """The default launch shapes are the measured best ones (see the policy
     in lb_engine.hip); a change of the policy shows up here."""
     walls = dict(boundary="couette", u_wall=0.005) if precision.endswith("-couette") else {}
@@ -323,6 +324,7 @@ def test_default_tile_policy(precision, nx, ny, seg_h, grp, pf):
     assert info["seg_h"] == seg_h, info
     assert info["tiles_per_group"] == grp, info
     assert info["prefetch"] == pf, info
+    assert info["stream_stores"] == nt, info
     assert info["ntiles"] == info["nstrips"] * info["nsegs"]
     lat.close()
 
