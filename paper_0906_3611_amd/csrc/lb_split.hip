@@ -220,7 +220,13 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
       constexpr int j = decltype(J)::value;
       const int k = k0 + j;
       if (k >= K) return;
-      if (!PF) pull_row(k, fr[j], rv[j]);
+      if (!PF) {
+        // issued at a raised wave priority, so the row's loads leave ahead
+        // of the collisions the SIMD's other waves are in
+        __builtin_amdgcn_s_setprio(3);
+        pull_row(k, fr[j], rv[j]);
+        __builtin_amdgcn_s_setprio(0);
+      }
       // rho_s and psi_s of the pulled row into ring slot k % 5; the ring
       // items go through LDS to lanes 0..3, which sum them in the same order
       CT rho = fr[j][0];
