@@ -221,11 +221,12 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
       const int k = k0 + j;
       if (k >= K) return;
       if (!PF) {
-        // issued at a raised wave priority, so the row's loads leave ahead
-        // of the collisions the SIMD's other waves are in
+        // From the row's loads to the row barrier the wave runs at a raised
+        // priority: the group's waves meet at that barrier, so the slowest
+        // one's way to it paces the group, while the collision after it can
+        // give way to the SIMD's other waves.
         __builtin_amdgcn_s_setprio(3);
         pull_row(k, fr[j], rv[j]);
-        __builtin_amdgcn_s_setprio(0);
       }
       // rho_s and psi_s of the pulled row into ring slot k % 5; the ring
       // items go through LDS to lanes 0..3, which sum them in the same order
@@ -253,6 +254,7 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
         ring_r[s][slot * W + rpos] = acc;
       }
       __syncthreads();  // both species' row k is in the ring
+      if (!PF) __builtin_amdgcn_s_setprio(0);
       if (PF && k + PF < K) pull_row(k + PF, fr[(j + PF) % NSET], rv[(j + PF) % NSET]);
       if (k >= 4) {
         constexpr int jc = (j + NSET - 2) % NSET;  // set of march row k - 2
