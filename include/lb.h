@@ -257,7 +257,9 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
  *     (0, 1 or 2; larger values mean 2; the moment storage ignores it).
  *     Default 1, and 0 where tiles are grouped or the moment storage
  *     exceeds the Infinity Cache.
- *   stream_stores: nontemporal population stores.
+ *   stream_stores: nontemporal population stores.  Default on where both
+ *     population buffers exceed the 256 MB Infinity Cache (FP64: twice it,
+ *     since its march reads back what plain stores left there).
  *   use_graph: replay lb_step as captured two-step HIP graphs (default 0:
  *     on MI355X under ROCm 7 a replayed step measured 2.3-2.5 us longer than
  *     a plain launch of the same kernel, so graphs only pay where the caller's
