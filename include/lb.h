@@ -255,8 +255,8 @@ int lb_get_launch_info(const lb_lattice* lat, lb_launch_info* out);
  *     averages carry on.
  *   prefetch: rows whose loads are in flight ahead of the current one
  *     (0, 1 or 2; larger values mean 2; the moment storage ignores it).
- *     Default 1, and 0 where tiles are grouped or the moment storage
- *     exceeds the Infinity Cache.
+ *     Default 1 (FP64: 2), and 0 where tiles are grouped or the moment
+ *     storage exceeds the Infinity Cache.
  *   stream_stores: nontemporal population stores.  Default on where both
  *     population buffers exceed the 256 MB Infinity Cache (FP64: twice it,
  *     since its march reads back what plain stores left there).

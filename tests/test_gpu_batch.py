@@ -309,9 +309,9 @@ def test_multi_chunk_observables_are_order_fixed(precision):
     ("fp32dev-couette", 4096, 1024, 32, 4, 0, 1),
     ("fp32dev", 4096, 4096, 128, 4, 0, 1),   # taller segments keep the halo rows in L2
     ("fp32dev", 128, 128, 4, 1, 1, 0),       # too small to fill the GPU: shortest march
-    ("fp64", 1024, 1024, 16, 1, 1, 0),       # ~1024 tiles; under twice the Infinity Cache
-    ("fp64", 4096, 1024, 64, 1, 1, 1),
-    ("fp64", 4096, 4096, 256, 1, 1, 1),
+    ("fp64", 1024, 1024, 16, 1, 2, 0),       # ~1024 tiles; under twice the Infinity Cache
+    ("fp64", 4096, 1024, 64, 1, 2, 1),
+    ("fp64", 4096, 4096, 256, 1, 2, 1),
     ("fp32mom", 4096, 4096, 32, 1, 0, 1),    # issue-bound: at most 32-row segments
     ("fp32mom", 128, 128, 4, 1, 1, 0),
 ])
