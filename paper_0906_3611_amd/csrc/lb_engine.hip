@@ -320,8 +320,8 @@ void choose_default_variant(Engine& E) {
   // exceed the 256 MB Infinity Cache.  A one-row prefetch for the
   // population storages with one tile per workgroup: FP32 deviations (one
   // wave per species) step 1.6-3.7% faster with it than without at 1024^2 to
-  // 4096^2, periodic and with walls; FP64 (one wave per SIMD) likewise.
-  // Grouped tiles step 1.5-4% faster without it (2048^2 to 8192 x 1024,
+  // 4096^2, periodic and with walls; FP64 (one wave per SIMD) likewise, and
+  // more so with two rows (below).  Grouped tiles step 1.5-4% faster without it (2048^2 to 8192 x 1024,
   // periodic and with walls; 1024 x 4096 and 2048 x 1024 the same): the
   // group's eight waves meet at every row's barrier, and loads issued
   // there, all waves at once, gain nothing from being issued a row early.
