@@ -220,14 +220,13 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
       constexpr int j = decltype(J)::value;
       const int k = k0 + j;
       if (k >= K) return;
-      if (!PF) {
-        // From the row's loads to the row barrier the wave runs at a raised
-        // priority: the group's waves meet at that barrier, so the slowest
-        // one's way to it paces the group, while the collision after it can
-        // give way to the SIMD's other waves.
-        __builtin_amdgcn_s_setprio(3);
-        pull_row(k, fr[j], rv[j]);
-      }
+      // From the row's start to the row barrier (and, with prefetch, to the
+      // issue of the next rows' loads just after it) the wave runs at a
+      // raised priority: the workgroup's waves meet at that barrier, so the
+      // slowest one's way to it paces them all, while the collision after it
+      // can give way to the SIMD's other waves.
+      __builtin_amdgcn_s_setprio(3);
+      if (!PF) pull_row(k, fr[j], rv[j]);
       // rho_s and psi_s of the pulled row into ring slot k % 5; the ring
       // items go through LDS to lanes 0..3, which sum them in the same order
       CT rho = fr[j][0];
@@ -254,8 +253,8 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
         ring_r[s][slot * W + rpos] = acc;
       }
       __syncthreads();  // both species' row k is in the ring
-      if (!PF) __builtin_amdgcn_s_setprio(0);
       if (PF && k + PF < K) pull_row(k + PF, fr[(j + PF) % NSET], rv[(j + PF) % NSET]);
+      __builtin_amdgcn_s_setprio(0);
       if (k >= 4) {
         constexpr int jc = (j + NSET - 2) % NSET;  // set of march row k - 2
         const CT(&f)[9] = fr[jc];
