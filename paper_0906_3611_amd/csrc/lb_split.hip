@@ -221,13 +221,13 @@ __global__ __launch_bounds__(2 * kWave * NSUB) void k_split(const LaunchArgs a) 
       const int k = k0 + j;
       if (k >= K) return;
       // From the row's start to the row barrier (and, with prefetch, to the
-      // issue of the next rows' loads just after it) the wave runs at a
+      // issue of row k + PF's loads just after it) the wave runs at a
       // raised priority: the workgroup's waves meet at that barrier, so the
       // slowest one's way to it paces them all, while the collision after it
       // can give way to the SIMD's other waves.
       __builtin_amdgcn_s_setprio(3);
       if (!PF) pull_row(k, fr[j], rv[j]);
-      // rho_s and psi_s of the pulled row into ring slot k % 5; the ring
+      // rho_s and psi_s of the pulled row into ring slot k % kSRing; the ring
       // items go through LDS to lanes 0..3, which sum them in the same order
       CT rho = fr[j][0];
 #pragma unroll
